@@ -1,0 +1,360 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these retype the oracle's own formulas: they check hand-derived bins
+(tests/golden/edge_pairs.txt), exact totals, invariances, closed forms that
+follow from the estimator's definition, library routines (numpy covariance,
+Legendre quadrature) and the paper's analytic covariance for uniform data.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import mockgen
+from tests.fixtures import edge_pairs, two_point_catalogues
+
+
+# ---------------------------------------------------------------------------
+# pair counts: hand-derived edge cases
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("scale", [1, 3, 4096, 2 ** 18 // 5])
+def test_edge_pairs_fixture(oracle_mod, scale):
+    for row in edge_pairs():
+        a, b, edges, box = two_point_catalogues(row, scale=scale)
+        n_mu = row["n_mu"]
+        got = oracle_mod.count_pairs(a, b, edges, n_mu, box, row["los"])
+        exp = np.zeros((len(edges) - 1, n_mu), dtype=np.uint64)
+        if row["k"] >= 0:
+            exp[row["k"], row["m"]] = 1
+        assert np.array_equal(got, exp), (row["note"], scale)
+        # the same two points as one catalogue: the single unordered pair
+        both = np.concatenate([a, b], axis=1)
+        got2 = oracle_mod.count_pairs(both, None, edges, n_mu, box, row["los"])
+        assert np.array_equal(got2, exp), (row["note"], scale, "auto")
+
+
+def test_edge_pairs_translation(oracle_mod):
+    """z line of sight: bins do not change under translation (open and periodic)."""
+    for row in edge_pairs():
+        if row["los"] != "z":
+            continue
+        for shift in [(5, -7, 11), (123456, 654321, -222222)]:
+            a, b, edges, box = two_point_catalogues(row, scale=7, shift=shift)
+            got = oracle_mod.count_pairs(a, b, edges, row["n_mu"], box, "z")
+            exp = np.zeros_like(got)
+            if row["k"] >= 0:
+                exp[row["k"], row["m"]] = 1
+            assert np.array_equal(got, exp), (row["note"], shift)
+
+
+# ---------------------------------------------------------------------------
+# pair counts: totals, invariances, union identity
+# ---------------------------------------------------------------------------
+
+def _rand_pts(seed, n, lo, hi):
+    r = np.random.default_rng(seed)
+    return r.integers(lo, hi, size=(3, n)).astype(np.int32)
+
+
+@pytest.mark.parametrize("los", ["z", "mid"])
+def test_totals_open_geometry(oracle_mod, los):
+    """With the last edge beyond the largest separation every pair is
+    counted once: N(N-1)/2 auto pairs, N_a N_b cross pairs."""
+    a = _rand_pts(1, 700, -3000, 3000)
+    b = _rand_pts(2, 500, -3000, 3000)
+    edges = [0, 1000, 4000, 12000]
+    for n_mu in (1, 7, 50):
+        dd = oracle_mod.count_pairs(a, None, edges, n_mu, 0, los)
+        dr = oracle_mod.count_pairs(a, b, edges, n_mu, 0, los)
+        assert int(dd.sum()) == 700 * 699 // 2
+        assert int(dr.sum()) == 700 * 500
+
+
+def test_totals_periodic_against_direct_distance_count(oracle_mod):
+    """Sum over mu bins equals the number of pairs with e_0 <= r < e_n,
+    counted here with a float64 distance (no pair lies within 1e-6 of an
+    edge for these inputs, which the test asserts)."""
+    L = 100000
+    a = _rand_pts(3, 400, 0, L)
+    edges = np.array([0, 3000, 9000, 20000, 30000])
+    got = oracle_mod.count_pairs(a, None, edges, 9, L, "z").sum(axis=1)
+    x = a.astype(np.float64)
+    s = x[:, None, :] - x[:, :, None]
+    s = (s + L / 2) % L - L / 2
+    r = np.sqrt((s ** 2).sum(axis=0))
+    iu = np.triu_indices(a.shape[1], 1)
+    rr = r[iu]
+    assert np.min(np.abs(rr[:, None] - edges[None, :])) > 1e-6
+    exp = np.histogram(rr, bins=edges.astype(np.float64))[0]
+    assert np.array_equal(got.astype(np.int64), exp)
+
+
+def test_invariances_periodic(oracle_mod):
+    L = 1 << 20
+    a = _rand_pts(4, 600, 0, L)
+    b = _rand_pts(5, 500, 0, L)
+    edges = np.arange(0, 11) * 20000
+    n_mu = 12
+    base_dd = oracle_mod.count_pairs(a, None, edges, n_mu, L)
+    base_dr = oracle_mod.count_pairs(a, b, edges, n_mu, L)
+    # translation by an integer vector modulo L
+    t = np.array([[123457], [L - 5], [777777]])
+    at, bt = (a + t) % L, (b + t) % L
+    assert np.array_equal(oracle_mod.count_pairs(at, None, edges, n_mu, L), base_dd)
+    assert np.array_equal(oracle_mod.count_pairs(at, bt, edges, n_mu, L), base_dr)
+    # swapping x and y (z line of sight unchanged)
+    assert np.array_equal(oracle_mod.count_pairs(a[[1, 0, 2]], b[[1, 0, 2]], edges, n_mu, L), base_dr)
+    # reflecting z -> -z (mod L)
+    ar, br = a.copy(), b.copy()
+    ar[2] = (L - ar[2]) % L
+    br[2] = (L - br[2]) % L
+    assert np.array_equal(oracle_mod.count_pairs(ar, br, edges, n_mu, L), base_dr)
+    # point order
+    p = np.random.default_rng(0).permutation(a.shape[1])
+    assert np.array_equal(oracle_mod.count_pairs(a[:, p], None, edges, n_mu, L), base_dd)
+    # cross counts are symmetric in the two catalogues
+    assert np.array_equal(oracle_mod.count_pairs(b, a, edges, n_mu, L), base_dr)
+
+
+@pytest.mark.parametrize("box,los", [(1 << 20, "z"), (0, "z"), (0, "mid")])
+def test_union_identity(oracle_mod, box, los):
+    """DD(A u B) = DD(A) + DD(B) + DR(A, B)."""
+    lo, hi = (0, box) if box else (1 << 18, 1 << 19)
+    a = _rand_pts(6, 500, lo, hi)
+    b = _rand_pts(7, 400, lo, hi)
+    edges = np.arange(0, 9) * 15000
+    ab = np.concatenate([a, b], axis=1)
+    lhs = oracle_mod.count_pairs(ab, None, edges, 10, box, los)
+    rhs = (oracle_mod.count_pairs(a, None, edges, 10, box, los)
+           + oracle_mod.count_pairs(b, None, edges, 10, box, los)
+           + oracle_mod.count_pairs(a, b, edges, 10, box, los))
+    assert np.array_equal(lhs, rhs)
+
+
+def test_midpoint_rotation_invariance(oracle_mod):
+    """Midpoint line of sight: a rotation by 90 degrees about any axis through
+    the observer permutes and negates coordinates and keeps every bin."""
+    a = _rand_pts(8, 300, -(1 << 20), 1 << 20)
+    b = _rand_pts(9, 300, -(1 << 20), 1 << 20)
+    edges = np.arange(0, 9) * 150000
+    base = oracle_mod.count_pairs(a, b, edges, 10, 0, "mid")
+    rot = lambda p: np.stack([-p[1], p[0], p[2]]).astype(np.int32)
+    assert np.array_equal(oracle_mod.count_pairs(rot(a), rot(b), edges, 10, 0, "mid"), base)
+    refl = lambda p: np.stack([p[0], p[1], -p[2]]).astype(np.int32)
+    assert np.array_equal(oracle_mod.count_pairs(refl(a), refl(b), edges, 10, 0, "mid"), base)
+
+
+def test_uniform_counts_match_shell_volume(oracle_mod):
+    """Uniform points in a periodic box: E[RR_km] = N(N-1)/2 * G_p(k, m), with
+    G_p = (4pi/3)(r_k+1^3 - r_k^3)/(L^3 n_mu) (mu uniform in [0, 1] for an
+    isotropic separation).  Checked with a chi-square over the bins."""
+    L = 1 << 22
+    n = 3000
+    pts = mockgen.uniform_box(np.random.default_rng(11), n, L)
+    edges = np.linspace(0, L // 4, 9).astype(np.int64)
+    n_mu = 5
+    got = oracle_mod.count_pairs(pts, None, edges, n_mu, L).astype(np.float64)
+    exp = n * (n - 1) / 2 * oracle_mod.shell_pair_fraction(edges, n_mu, L)
+    chi2 = float(((got - exp) ** 2 / exp).sum())
+    dof = got.size
+    assert abs(chi2 - dof) < 6 * math.sqrt(2 * dof), chi2
+    # the total within r_max has a relative scatter of about 1/sqrt(pairs)
+    assert abs(got.sum() / exp.sum() - 1) < 0.02
+
+
+# ---------------------------------------------------------------------------
+# estimator
+# ---------------------------------------------------------------------------
+
+def test_ls_data_equals_random_closed_form(oracle_mod):
+    """With the random catalogue equal to the data (R = D, N points):
+    DR(D, D) = 2 DD away from r = 0 and RR = DD, so the estimator is
+    (dd - 2 dr)/rr + 1 = 2 - 2 (N-1)/N = 2/N exactly.  The same holds for the
+    split M = 2 estimate with R1 = R2 = D."""
+    n = 400
+    L = 1 << 20
+    d = _rand_pts(12, n, 0, L)
+    edges = np.arange(1, 12) * 30000           # e_0 > 0: no zero-separation pairs
+    DD = oracle_mod.count_pairs(d, None, edges, 4, L)
+    DR = oracle_mod.count_pairs(d, d, edges, 4, L)
+    assert np.array_equal(DR, 2 * DD)
+    xi1 = oracle_mod.ls_split(DD, [DR], [DD], n, [n])
+    xi2 = oracle_mod.ls_split(DD, [DR, DR], [DD, DD], n, [n, n])
+    ok = DD > 0
+    assert np.allclose(xi1[ok], 2.0 / n, rtol=1e-12, atol=0)
+    assert np.allclose(xi2[ok], 2.0 / n, rtol=1e-12, atol=0)
+    assert np.all(np.isnan(xi1[~ok]))
+
+
+def test_ls_doubled_random_closed_form(oracle_mod):
+    """Random catalogue = every data point twice (N_r = 2N): DR = 2 DR(D,D),
+    RR = 4 DD (+N coincident pairs at r = 0, excluded by e_0 > 0).  Then
+    dd = 2DD/(N(N-1)), dr = 2DD/N^2, rr = 4DD/(N(2N-1)), and
+    xi = (2N-1)/(2(N-1)) - (2N-1)/N + 1, independent of the counts.
+    This fixes the DR and RR normalisations for N_r != N_d."""
+    n = 300
+    L = 1 << 20
+    d = _rand_pts(13, n, 0, L)
+    r = np.concatenate([d, d], axis=1)
+    edges = np.arange(1, 10) * 40000
+    DD = oracle_mod.count_pairs(d, None, edges, 3, L)
+    DR = oracle_mod.count_pairs(d, r, edges, 3, L)
+    RR = oracle_mod.count_pairs(r, None, edges, 3, L)
+    assert np.array_equal(RR, 4 * DD)
+    xi = oracle_mod.ls_split(DD, [DR], [RR], n, [2 * n])
+    exp = (2 * n - 1) / (2 * (n - 1)) - (2 * n - 1) / n + 1
+    ok = DD > 0
+    assert np.allclose(xi[ok], exp, rtol=1e-12, atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# multipoles
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n_mu", [1, 5, 10, 50, 100])
+def test_legendre_weights_against_quadrature(oracle_mod, n_mu):
+    """W[l, m] against Gauss-Legendre quadrature of (2l+1) P_l on each bin
+    (numpy's Legendre module: an independent evaluation of P_l)."""
+    from numpy.polynomial import legendre as npl
+    W = oracle_mod.legendre_weights(n_mu)
+    xg, wg = npl.leggauss(8)
+    for li, ell in enumerate((0, 2, 4)):
+        c = np.zeros(ell + 1)
+        c[ell] = 1.0
+        for m in range(n_mu):
+            a, b = m / n_mu, (m + 1) / n_mu
+            x = 0.5 * (b - a) * xg + 0.5 * (b + a)
+            q = (2 * ell + 1) * 0.5 * (b - a) * np.sum(wg * npl.legval(x, c))
+            assert abs(W[li, m] - q) < 1e-14
+    # sums over mu: integral of P_0 over [0,1] is 1, of P_2 and P_4 is 0
+    assert abs(W[0].sum() - 1) < 1e-14
+    assert abs(W[1].sum()) < 1e-13 and abs(W[2].sum()) < 1e-13
+
+
+def test_multipoles_of_legendre_shapes(oracle_mod):
+    """A xi that is the bin average of c0 + c2 P_2 + c4 P_4 gives back
+    (c0, c2, c4) as n_mu grows (orthogonality of P_l); constant xi gives
+    exactly (c, 0, 0)."""
+    from numpy.polynomial import legendre as npl
+    n_mu = 2000
+    e = np.arange(n_mu + 1) / n_mu
+    coef = np.array([0.7, 0.0, -1.3, 0.0, 0.4])
+    F = npl.legval(e, npl.legint(coef))
+    xi = ((F[1:] - F[:-1]) * n_mu)[None, :].repeat(3, axis=0)
+    mp = oracle_mod.multipoles(xi)
+    assert np.allclose(mp[:, 0], [0.7, -1.3, 0.4], atol=2e-6)
+    const = np.full((4, 10), 0.25)
+    mc = oracle_mod.multipoles(const)
+    assert np.allclose(mc[0], 0.25, atol=1e-15) and np.allclose(mc[1:], 0.0, atol=1e-15)
+
+
+def test_data_vector_layout(oracle_mod):
+    xi = np.arange(12.0).reshape(3, 4)
+    v = oracle_mod.data_vector(xi)
+    assert v.shape == (12 + 9,)
+    assert np.array_equal(v[:12], xi.ravel())
+    assert np.allclose(v[12:15], xi.mean(axis=1))        # xi_0 = bin average over mu
+
+
+# ---------------------------------------------------------------------------
+# covariance and linear construction
+# ---------------------------------------------------------------------------
+
+def test_sample_cov_matches_numpy(oracle_mod):
+    V = np.random.default_rng(3).normal(size=(57, 9)) * np.arange(1, 10)
+    assert np.allclose(oracle_mod.sample_cov(V), np.cov(V, rowvar=False), rtol=1e-13, atol=1e-15)
+
+
+def _general_reconstruction(Ca, Cb, Ma, Mb):
+    """A and B from two random-catalogue sizes M_a < M_b (Sect. 2.2, general
+    form): A = (M_b C(M_b) - M_a C(M_a)) / (M_b - M_a),
+    B = M_a M_b (C(M_a) - C(M_b)) / (M_b - M_a)."""
+    A = (Mb * Cb - Ma * Ca) / (Mb - Ma)
+    B = Ma * Mb * (Ca - Cb) / (Mb - Ma)
+    return A, B
+
+
+@pytest.mark.parametrize("m_a", [1, 2, 3])
+def test_lc_equals_general_reconstruction(oracle_mod, m_a):
+    """The component matrices of the linear construction (Sect. 2.3) are the
+    general two-size reconstruction of Sect. 2.2 at M_b = 2 M_a."""
+    r = np.random.default_rng(m_a)
+    X = r.normal(size=(6, 6))
+    Ca = X @ X.T
+    Cb = 0.6 * Ca + 0.1 * np.eye(6)
+    A, B, C = oracle_mod.linear_construction(Ca, Cb, m_a, 50.0)
+    A2, B2 = _general_reconstruction(Ca, Cb, m_a, 2 * m_a)
+    assert np.allclose(A, A2, rtol=1e-13) and np.allclose(B, B2, rtol=1e-13)
+
+
+def test_lc_recovers_exact_model(oracle_mod):
+    """If C(M) = A0 + B0/M exactly, C^a = C(M_a) and C^b = C(2 M_a) give back
+    A0, B0 and C(M) for every M, including M -> infinity."""
+    r = np.random.default_rng(5)
+    X, Y = r.normal(size=(5, 5)), r.normal(size=(5, 5))
+    A0, B0 = X @ X.T, Y @ Y.T
+    for m_a in (1, 4):
+        Ca, Cb = A0 + B0 / m_a, A0 + B0 / (2 * m_a)
+        for M in (1.0, 2.0, 7.5, 50.0, np.inf):
+            A, B, C = oracle_mod.linear_construction(Ca, Cb, m_a, M)
+            assert np.allclose(A, A0, rtol=1e-12, atol=1e-12)
+            assert np.allclose(B, B0, rtol=1e-12, atol=1e-12)
+            exp = A0 if np.isinf(M) else A0 + B0 / M
+            assert np.allclose(C, exp, rtol=1e-12, atol=1e-12)
+        # the construction reproduces its inputs at M = M_a and M = 2 M_a
+        assert np.allclose(oracle_mod.linear_construction(Ca, Cb, m_a, m_a)[2], Ca)
+        assert np.allclose(oracle_mod.linear_construction(Ca, Cb, m_a, 2 * m_a)[2], Cb)
+
+
+def test_check_matrix(oracle_mod):
+    rep = oracle_mod.check_matrix(np.diag([3.0, 1.0, 2.0]))
+    assert rep == {"chol_ok": 1, "n_neg_eig": 0, "min_eig": 1.0, "max_eig": 3.0}
+    rep = oracle_mod.check_matrix(np.diag([3.0, -1.0, -2.0]))
+    assert rep["chol_ok"] == 0 and rep["n_neg_eig"] == 2 and rep["min_eig"] == -2.0
+
+
+# ---------------------------------------------------------------------------
+# statistical pin: uniform data with independent randoms (Sect. 4.2, 5.1)
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def poisson_mock_vectors(oracle_mod):
+    n_mock, n, L = 240, 800, 1 << 20
+    xyz, off, ids = mockgen.independent_poisson_mocks(77, n_mock, n, L)
+    edges = np.linspace(L // 40, L // 8, 9).astype(np.int64)
+    n_mu = 1
+    V = []
+    for m in range(n_mock):
+        cd, c1, c2 = (xyz[:, off[i]:off[i + 1]] for i in ids[m])
+        DD, DR1, DR2, RR1, RR2 = oracle_mod.mock_counts(cd, c1, c2, edges, n_mu, L, "z")
+        x1 = oracle_mod.ls_split(DD, [DR1], [RR1], n, [n]).ravel()
+        x2 = oracle_mod.ls_split(DD, [DR2], [RR2], n, [n]).ravel()
+        y = oracle_mod.ls_split(DD, [DR1, DR2], [RR1, RR2], n, [n, n]).ravel()
+        V.append([x1, x2, y])
+    G_p = oracle_mod.shell_pair_fraction(edges, n_mu, L).ravel()
+    return np.array(V), n, G_p
+
+
+def test_uniform_data_xi_unbiased(poisson_mock_vectors):
+    V, n, G_p = poisson_mock_vectors
+    mean = V[:, 2].mean(axis=0)
+    sd = V[:, 2].std(axis=0, ddof=1) / math.sqrt(V.shape[0])
+    assert np.all(np.abs(mean) < 4.5 * sd)
+
+
+def test_lc_diagonal_matches_random_theory(oracle_mod, poisson_mock_vectors):
+    """diag C^LC(M) for uniform data against the paper's analytic variance
+    (2/(N_d(N_d-1)) + 4/(N_d N_r) + 2/(N_r(N_d-1)))/G_p with N_r = M N_d.
+    At M = 1 and M = 2 the construction returns C^a and C^b; M = infinity is A.
+    The tolerance is about 4 standard errors of the bin-averaged ratio."""
+    V, n, G_p = poisson_mock_vectors
+    A, B, C, Ca, Cb = oracle_mod.lc_from_vectors(V, 1, 50.0)
+    for M, tol in ((1.0, 0.08), (2.0, 0.09), (50.0, 0.25), (np.inf, 0.3)):
+        CM = A if np.isinf(M) else A + B / M
+        if np.isinf(M):
+            theory = 2.0 / (n * (n - 1.0)) / G_p
+        else:
+            theory = oracle_mod.random_theory_variance(n, M * n, G_p)
+        ratio = np.diag(CM) / theory
+        assert abs(ratio.mean() - 1.0) < tol, (M, ratio)
