@@ -1,0 +1,211 @@
+/*
+ * lc.h -- C ABI of the MI355X (gfx950) linear-construction covariance path.
+ *
+ * The path follows the paper's problem statement (Sect. 2.1-2.3, 4.3):
+ *   mocks D, each with two random catalogues R1 and R2 of about the data
+ *   size; pair counts DD, DR_i and RR_i in (r, mu) bins; the split
+ *   Landy-Szalay estimate for (D,R1), (D,R2) and (D, R1 u R2); its Legendre
+ *   multipoles l = 0, 2, 4; the sample covariances C^a, C^b over the mocks;
+ *   and the linear construction C^LC = A + B/M with A = 2C^b - C^a,
+ *   B = 2 M_a (C^a - C^b).
+ *
+ * Conventions for every call:
+ *   - Return value is an lc_status: 0 = LC_OK, negative on error.  No call
+ *     aborts or exits.  lc_last_error() gives a message for the calling
+ *     thread's last failed call.
+ *   - "DEVICE" pointers are HIP device memory on the current device, owned
+ *     by the caller; "HOST" arrays are read before the call returns and are
+ *     not retained.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Calls are
+ *     asynchronous on that stream unless stated otherwise.
+ *   - Every error that can be detected on the host is reported before any
+ *     work is enqueued.  An asynchronous HIP fault surfaces as LC_ERR_HIP.
+ *   - Coordinates are int32 in units of 2^-12 Mpc/h.  Periodic boxes:
+ *     0 <= x < box_units <= 2^24.  Open geometry: |x| < 2^24.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lc_status;
+
+#define LC_OK            0
+#define LC_ERR_INVALID  -1  /* NULL pointer, bad size, bad edges, bad ids, bad mode */
+#define LC_ERR_RANGE    -2  /* coordinate outside the geometry; r_max too large for the box */
+#define LC_ERR_OVERFLOW -3  /* a size or index exceeds what the layout supports */
+#define LC_ERR_HIP      -4  /* HIP runtime error (message holds hipGetErrorString) */
+#define LC_ERR_NOMEM    -5  /* device or pinned allocation failed */
+
+#define LC_LOS_Z    0       /* plane-parallel, line of sight = z axis (Sect. 4.1) */
+#define LC_LOS_MID  1       /* line of sight = pair midpoint seen from the origin (open geometry) */
+
+#define LC_MAX_BINS 8192    /* n_r * n_mu */
+#define LC_MAX_NMU  1024
+
+/* Thread-local message of the last failed call; valid until the next lc_* call. */
+const char* lc_last_error(void);
+
+/*
+ * Separation binning (Sect. 4.3: 2D correlation function in r and mu).
+ *   r bin k:  r_edges[k] <= r < r_edges[k+1]; pairs outside [r_edges[0],
+ *             r_edges[n_r]) are not counted.
+ *   mu bin m: m = floor(n_mu * |mu|), the last bin closed at |mu| = 1;
+ *             mu is the cosine between the line of sight and the pair
+ *             separation; a pair at zero separation goes to mu bin 0.
+ * Every comparison is exact: it equals the integer rule
+ *   r_edges[k]^2 <= d^2 < r_edges[k+1]^2 and the largest m < n_mu with
+ *   m^2 d^2 <= n_mu^2 s_z^2 (midpoint: m^2 d^2 |l|^2 <= n_mu^2 (s.l)^2, l = x_i + x_j).
+ */
+typedef struct {
+    int32_t periodic;         /* 1: periodic cube [0, box_units)^3, minimal image; 0: open */
+    int32_t box_units;        /* periodic side, even, <= 2^24; ignored when open */
+    int32_t los;              /* LC_LOS_Z or LC_LOS_MID (MID requires periodic = 0) */
+    int32_t n_r;              /* >= 1 */
+    const int32_t* r_edges;   /* HOST, n_r + 1 strictly increasing values >= 0;
+                                 periodic: r_edges[n_r] < box_units / 2; open: < 2^25 */
+    int32_t n_mu;             /* 1 .. LC_MAX_NMU, n_r * n_mu <= LC_MAX_BINS */
+} lc_binning;
+
+/*
+ * Chaining mesh of many catalogues (counting sort by cell, one grid shared
+ * by all catalogues).  Opaque; owned by the library; immutable once built.
+ */
+typedef struct lc_cells lc_cells;
+
+/*
+ * lc_build_cells: sort every catalogue into a shared chaining mesh.
+ *   xyz          DEVICE int32 SoA [3][n_total]: x[0..n), y[0..n), z[0..n);
+ *                catalogues stored back to back.  Not retained.
+ *   cat_offsets  HOST int64 [n_cat + 1]; [0] = 0, non-decreasing,
+ *                [n_cat] = n_total.  Catalogue c = points [off[c], off[c+1]).
+ *   b            binning the mesh will be used with (geometry, r_max).
+ *   cell_units   requested cell side in coordinate units; 0 = library default
+ *                (about r_max / 2).  Larger values are rounded to fit the box.
+ *   out          receives the mesh; free with lc_free_cells.
+ * Synchronises `stream` once, to read the device range-check word (a point
+ * outside the geometry returns LC_ERR_RANGE and no mesh).
+ */
+lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
+                         int32_t n_cat, const lc_binning* b, int32_t cell_units,
+                         void* stream, lc_cells** out);
+void lc_free_cells(lc_cells* cells);
+
+/* Mesh facts (HOST): grid cells per axis, cell side in units, points. */
+typedef struct {
+    int32_t n_cat;
+    int32_t grid[3];
+    double cell_side[3];
+    int64_t n_total;
+    int64_t bytes;            /* device memory held by the mesh */
+} lc_cells_info;
+lc_status lc_cells_get_info(const lc_cells* cells, lc_cells_info* info);
+
+/*
+ * A counting task: catalogues a and b.  a == b: unordered pairs i < j of
+ * one catalogue (DD, and RR of one random sub-catalogue -- pairs between
+ * different sub-catalogues are never formed, Sect. 2.1 "split");
+ * a != b: every pair (i in a, j in b) (DR).
+ */
+typedef struct { int32_t cat_a, cat_b; } lc_task;
+
+/* lc_pair_count_batch modes */
+#define LC_PERSISTENT   0   /* one persistent launch over a work queue of (task, cell) tiles */
+#define LC_PER_TASK     1   /* baseline: one launch per task, sized to that task */
+#define LC_GRAPH        2   /* flag: capture the launch sequence in a hipGraph, cache, replay */
+#define LC_FORCE_EXACT  4   /* flag (testing): bin every pair with the integer rule only */
+
+/* Tuning knobs; NULL or 0 fields = library defaults. */
+typedef struct {
+    int32_t cells_per_item;   /* cells of one catalogue per work item */
+    int32_t waves_per_block;  /* 1, 2, 4, 8 */
+    int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
+    int32_t reserved;
+} lc_tuning;
+
+/*
+ * lc_pair_count_batch: add the (r, mu) pair counts of every task.
+ *   cells    mesh from lc_build_cells (built with the same geometry and
+ *            an r_max >= this binning's last edge).
+ *   tasks    HOST [n_tasks]; catalogue ids < n_cat.
+ *   b        binning; n_r * n_mu bins.
+ *   counts   DEVICE uint64 [n_tasks][n_r][n_mu], ADDED INTO (zero it first).
+ *   mode     LC_PERSISTENT or LC_PER_TASK, optionally | LC_GRAPH | LC_FORCE_EXACT.
+ *   tune     NULL for defaults.
+ *   stats    DEVICE uint64 [4] or NULL, ADDED INTO: candidate pair tests,
+ *            binned pairs, pairs resolved by the integer fallback, histogram
+ *            flushes.
+ * Asynchronous.  Counts are exact; the result does not depend on mode,
+ * tuning, or the order in which tiles run.
+ */
+lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
+                              const lc_binning* b, uint64_t* counts, int32_t mode,
+                              const lc_tuning* tune, uint64_t* stats, void* stream);
+
+/*
+ * lc_xi_multipoles: split Landy-Szalay estimates and their multipoles
+ * (Sect. 2.1, 2.3, 4.3), float64.
+ *   counts     DEVICE uint64 [n_tasks][n_r][n_mu] from lc_pair_count_batch.
+ *   tasks      HOST [n_tasks], as counted.
+ *   cat_sizes  HOST int64 [n_cat]: points per catalogue.
+ *   est        HOST int32 [n_mock][5]: task ids of DD, DR1, DR2, RR1, RR2 of
+ *              each mock; DD = (D,D), DR_i = (D,R_i), RR_i = (R_i,R_i).
+ *   xi         DEVICE double [n_mock][3][P], P = n_r*n_mu + 3*n_r, written.
+ *              Estimate 0 = (D,R1) with M = 1, 1 = (D,R2) with M = 1,
+ *              2 = (D, R1 u R2) split with M = 2.  Vector layout:
+ *              [xi(r,mu) r-major | xi_0(r) | xi_2(r) | xi_4(r)].
+ *   Normalisation: dd = DD/(N_d(N_d-1)/2), dr_i = DR_i/(N_d N_r,i),
+ *   rr_i = RR_i/(N_r,i(N_r,i-1)/2); xi = (dd - (2/M) sum dr_i)/((1/M) sum rr_i) + 1;
+ *   a bin with rr = 0 gives NaN.  Multipoles integrate P_l exactly over
+ *   every |mu| bin: xi_l(r) = sum_m (2l+1) [int_{mu_m}^{mu_m+1} P_l] xi(r, mu_m).
+ */
+lc_status lc_xi_multipoles(const uint64_t* counts, const lc_task* tasks, int32_t n_tasks,
+                           const int64_t* cat_sizes, int32_t n_cat, const int32_t* est,
+                           int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi,
+                           void* stream);
+
+/* lc_covariance precision */
+#define LC_FP64               0  /* float64 covariance products */
+#define LC_FP32_MFMA          1  /* float32 MFMA products, float64 mean/combination/check */
+#define LC_FP32_MFMA_CHECKED  2  /* as LC_FP32_MFMA and also the float64 path, for the report */
+
+/* Positive-definiteness report (Sect. 3: C^LC is not guaranteed to be
+ * positive definite; check its spectrum).  Block 0 = the (r, mu) part
+ * [0, n_r*n_mu), block 1 = the multipole part; the full vector is singular
+ * (multipoles are linear in xi(r, mu)), so blocks are checked separately. */
+typedef struct {
+    int32_t chol_ok[2];       /* 1: Cholesky succeeded (all pivots > 0) */
+    int32_t n_neg_eig[2];     /* eigenvalues < 0 (Sturm count at 0); -1 if NaN present */
+    double min_eig[2];
+    double max_eig[2];
+    double rel_frob_vs_fp64[3]; /* ||X32 - X64||_F / ||X64||_F for C, A, B; -1 unless CHECKED */
+} lc_cov_report;
+
+/*
+ * lc_covariance: sample covariances over mocks and the linear construction.
+ *   xi        DEVICE double [n_mock][3][P] from lc_xi_multipoles, P = n_r*n_mu + 3*n_r.
+ *   n_mock    >= 2.
+ *   m_a       random/data size ratio of R1 and R2 (1 in the paper, Sect. 4.4).
+ *   M         target ratio; INFINITY gives A (the infinite-random limit).
+ *   A, B, C   DEVICE double [P][P] full symmetric, written; A and B may be NULL.
+ *             C^a = (Cov x + Cov x')/2, C^b = Cov y, Cov = sum (v - mean)(v - mean)^T / (N - 1).
+ *   rep       HOST or NULL.  Non-NULL runs the float64 Cholesky and
+ *             eigenvalue check of C on the device and synchronises `stream`.
+ * NaN entries of xi propagate to the affected rows and columns.
+ */
+lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n_mu,
+                        int32_t m_a, double M, int32_t precision,
+                        double* A, double* B, double* C, lc_cov_report* rep, void* stream);
+
+/* Release cached device buffers, graphs and pinned staging memory of the
+ * current device (they are otherwise kept until the process ends). */
+void lc_release_caches(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LC_H */

@@ -1,0 +1,443 @@
+// Chaining mesh: counting sort of every catalogue into one shared grid of
+// cells, so that pair counting only visits cells that can hold pairs closer
+// than r_max.  Steps: (open geometry) bounding box -> cell id and per-cell
+// histogram -> exclusive scan -> scatter of float64 points.
+#include <algorithm>
+#include <cmath>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+static constexpr int kLimit24 = 1 << 24;
+
+lc_status check_binning(const lc_binning* b) {
+    if (!b) return fail(LC_ERR_INVALID, "binning is NULL");
+    if (!b->r_edges) return fail(LC_ERR_INVALID, "binning.r_edges is NULL");
+    if (b->n_r < 1) return fail(LC_ERR_INVALID, "n_r = %d, must be >= 1", b->n_r);
+    if (b->n_mu < 1 || b->n_mu > LC_MAX_NMU)
+        return fail(LC_ERR_INVALID, "n_mu = %d, must be in [1, %d]", b->n_mu, LC_MAX_NMU);
+    if ((int64_t)b->n_r * b->n_mu > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "n_r * n_mu = %lld exceeds %d", (long long)b->n_r * b->n_mu,
+                    LC_MAX_BINS);
+    if (b->periodic != 0 && b->periodic != 1)
+        return fail(LC_ERR_INVALID, "periodic = %d, must be 0 or 1", b->periodic);
+    if (b->los != LC_LOS_Z && b->los != LC_LOS_MID)
+        return fail(LC_ERR_INVALID, "los = %d, must be LC_LOS_Z or LC_LOS_MID", b->los);
+    if (b->los == LC_LOS_MID && b->periodic)
+        return fail(LC_ERR_INVALID, "the midpoint line of sight needs open geometry");
+    if (b->r_edges[0] < 0) return fail(LC_ERR_INVALID, "r_edges[0] = %d < 0", b->r_edges[0]);
+    for (int k = 0; k < b->n_r; k++)
+        if (b->r_edges[k + 1] <= b->r_edges[k])
+            return fail(LC_ERR_INVALID, "r_edges not strictly increasing at %d", k);
+    const int64_t rmax = b->r_edges[b->n_r];
+    if (b->periodic) {
+        if (b->box_units < 2 || b->box_units > kLimit24 || (b->box_units & 1))
+            return fail(LC_ERR_INVALID, "box_units = %d must be even and in [2, 2^24]", b->box_units);
+        if (2 * rmax >= b->box_units)
+            return fail(LC_ERR_RANGE, "r_max = %lld must be < box/2 = %d", (long long)rmax,
+                        b->box_units / 2);
+    } else if (rmax >= (int64_t(1) << 25)) {
+        return fail(LC_ERR_RANGE, "r_max = %lld must be < 2^25 in open geometry", (long long)rmax);
+    }
+    return LC_OK;
+}
+
+int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out) {
+    // Two cells whose indices differ by d along an axis are at least
+    // (|d| - 1) * w apart on it (w = ext / n): offsets with
+    // sum max(|d|-1, 0)^2 w^2 >= r_max^2 cannot hold a binned pair.
+    double w[3];
+    int k[3];
+    for (int a = 0; a < 3; a++) {
+        w[a] = double(g.ext[a]) / double(g.n[a]);
+        k[a] = int(std::floor(double(r_max) / w[a])) + 1;
+        // beyond one full turn (periodic) or the grid (open) nothing new is reachable
+        k[a] = std::min(k[a], g.n[a]);
+    }
+    const double r2 = double(r_max) * double(r_max) * (1.0 + 1e-12);
+    std::vector<int4> pos, neg;
+    for (int dz = -k[2]; dz <= k[2]; dz++)
+        for (int dy = -k[1]; dy <= k[1]; dy++)
+            for (int dx = -k[0]; dx <= k[0]; dx++) {
+                if (!dx && !dy && !dz) continue;
+                int d[3] = {dx, dy, dz};
+                double s = 0;
+                for (int a = 0; a < 3; a++) {
+                    double m = std::max(std::abs(d[a]) - 1, 0) * w[a];
+                    s += m * m;
+                }
+                if (s >= r2) continue;
+                bool positive = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
+                (positive ? pos : neg).push_back(make_int4(dx, dy, dz, 0));
+            }
+    out.clear();
+    out.push_back(make_int4(0, 0, 0, 0));
+    out.insert(out.end(), pos.begin(), pos.end());
+    int n_half = int(out.size());
+    out.insert(out.end(), neg.begin(), neg.end());
+    return n_half;
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+// Bounding box of all points (open geometry) and the |x| < 2^24 check.
+__global__ void k_bbox(const int32_t* __restrict__ xyz, int64_t n, int32_t* __restrict__ box,
+                       unsigned* __restrict__ err) {
+    int mn[3] = {INT32_MAX, INT32_MAX, INT32_MAX}, mx[3] = {INT32_MIN, INT32_MIN, INT32_MIN};
+    bool bad = false;
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        for (int a = 0; a < 3; a++) {
+            int v = xyz[a * n + p];
+            mn[a] = min(mn[a], v);
+            mx[a] = max(mx[a], v);
+            bad |= (v <= -kLimit24) || (v >= kLimit24);
+        }
+    }
+    for (int a = 0; a < 3; a++) {
+        for (int o = 32; o > 0; o >>= 1) {
+            mn[a] = min(mn[a], __shfl_xor(mn[a], o));
+            mx[a] = max(mx[a], __shfl_xor(mx[a], o));
+        }
+    }
+    if ((threadIdx.x & 63) == 0) {
+        for (int a = 0; a < 3; a++) {
+            atomicMin(&box[a], mn[a]);
+            atomicMax(&box[3 + a], mx[a]);
+        }
+    }
+    if (bad) atomicOr(err, 1u);
+}
+
+__global__ void k_fill_box(int32_t* box) {
+    if (threadIdx.x < 3) box[threadIdx.x] = INT32_MAX;
+    else if (threadIdx.x < 6) box[threadIdx.x] = INT32_MIN;
+}
+
+__global__ void k_zero_u32(unsigned* p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+__device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, int32_t n_cat, int64_t p) {
+    // largest c with off[c] <= p (catalogues may be empty)
+    int32_t lo = 0, hi = n_cat;  // off[lo] <= p < off[hi]
+    while (hi - lo > 1) {
+        int32_t mid = (lo + hi) >> 1;
+        if (off[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ int32_t axis_cell(int32_t x, int32_t lo, int64_t ext, int32_t n) {
+    return int32_t((int64_t(x - lo) * n) / ext);
+}
+
+// Cell id per point and per-cell histogram; range check for periodic boxes.
+__global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
+                             int32_t n_cat, GridGeom g, int64_t* __restrict__ gid,
+                             unsigned* __restrict__ cnt, unsigned* __restrict__ err) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int32_t x = xyz[p], y = xyz[n + p], z = xyz[2 * n + p];
+        if (g.periodic) {
+            if (x < 0 || y < 0 || z < 0 || x >= g.box || y >= g.box || z >= g.box) {
+                atomicOr(err, 2u);
+                gid[p] = -1;
+                continue;
+            }
+        }
+        int32_t cx = axis_cell(x, g.lo[0], g.ext[0], g.n[0]);
+        int32_t cy = axis_cell(y, g.lo[1], g.ext[1], g.n[1]);
+        int32_t cz = axis_cell(z, g.lo[2], g.ext[2], g.n[2]);
+        int32_t c = find_cat(off, n_cat, p);
+        int64_t id = int64_t(c) * g.ncell + (int64_t(cz) * g.n[1] + cy) * g.n[0] + cx;
+        gid[p] = id;
+        atomicAdd(&cnt[id], 1u);
+    }
+}
+
+// Exclusive scan of uint32 cell counts into int64 starts.
+static constexpr int kScanThreads = 256;
+static constexpr int kScanItems = 8;
+static constexpr int kScanTile = kScanThreads * kScanItems;
+
+__device__ __forceinline__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[wid] = x;
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+    for (int w = 0; w < kScanThreads / 64; w++) {
+        if (w < wid) base += sh[w];
+        tot += sh[w];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+__global__ void k_scan_reduce(const unsigned* __restrict__ cnt, int64_t n, int64_t* __restrict__ bsum) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    int64_t s = 0;
+    for (int i = 0; i < kScanItems; i++)
+        if (base + i < n) s += cnt[base + i];
+    int64_t tot;
+    (void)block_exclusive_scan(s, sh, &tot);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(int64_t* __restrict__ bsum, int64_t nb, int64_t* __restrict__ grand) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kScanThreads) {
+        int64_t i = b0 + threadIdx.x;
+        int64_t v = i < nb ? bsum[i] : 0;
+        int64_t tot;
+        int64_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < nb) bsum[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) *grand = carry;
+}
+
+__global__ void k_scan_down(const unsigned* __restrict__ cnt, int64_t n, const int64_t* __restrict__ boff,
+                            int64_t* __restrict__ out) {
+    __shared__ int64_t sh[kScanThreads / 64];
+    int64_t base = int64_t(blockIdx.x) * kScanTile + threadIdx.x * kScanItems;
+    unsigned v[kScanItems];
+    int64_t s = 0;
+    for (int i = 0; i < kScanItems; i++) {
+        v[i] = base + i < n ? cnt[base + i] : 0u;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(s, sh, &tot) + boff[blockIdx.x];
+    for (int i = 0; i < kScanItems; i++) {
+        if (base + i < n) out[base + i] = ex;
+        ex += v[i];
+    }
+}
+
+__global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out[n] = *grand; }
+
+// Scatter: each point takes a slot in its cell (order inside a cell is free;
+// counts never depend on it).
+__global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ gid,
+                          const int64_t* __restrict__ cs, unsigned* __restrict__ cnt,
+                          double4* __restrict__ pts) {
+    for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
+         p += (int64_t)gridDim.x * blockDim.x) {
+        int64_t id = gid[p];
+        if (id < 0) continue;
+        unsigned r = atomicSub(&cnt[id], 1u) - 1u;
+        pts[cs[id] + r] = make_double4(double(xyz[p]), double(xyz[n + p]), double(xyz[2 * n + p]), 0.0);
+    }
+}
+
+static int grid_for(int64_t n, int threads, int n_cu) {
+    int64_t b = (n + threads - 1) / threads;
+    int64_t cap = int64_t(n_cu) * 16;
+    return int(std::max<int64_t>(1, std::min(b, cap)));
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+static void free_cells_mem(lc_cells* c) {
+    if (!c) return;
+    if (c->pts) (void)hipFree(c->pts);
+    if (c->cs) (void)hipFree(c->cs);
+    c->pts = nullptr;
+    c->cs = nullptr;
+}
+
+extern "C" void lc_free_cells(lc_cells* cells) {
+    if (!cells) return;
+    free_cells_mem(cells);
+    delete cells;
+}
+
+extern "C" lc_status lc_cells_get_info(const lc_cells* c, lc_cells_info* info) {
+    clear_error();
+    if (!c || !info) return fail(LC_ERR_INVALID, "NULL argument");
+    info->n_cat = c->n_cat;
+    for (int a = 0; a < 3; a++) {
+        info->grid[a] = c->g.n[a];
+        info->cell_side[a] = double(c->g.ext[a]) / double(c->g.n[a]);
+    }
+    info->n_total = c->n_total;
+    info->bytes = (int64_t)c->bytes;
+    return LC_OK;
+}
+
+extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
+                                    int32_t n_cat, const lc_binning* b, int32_t cell_units,
+                                    void* stream, lc_cells** out) {
+    clear_error();
+    if (!out) return fail(LC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    LC_TRY(check_binning(b));
+    if (n_cat < 1) return fail(LC_ERR_INVALID, "n_cat = %d, must be >= 1", n_cat);
+    if (!cat_offsets) return fail(LC_ERR_INVALID, "cat_offsets is NULL");
+    if (n_total < 0) return fail(LC_ERR_INVALID, "n_total < 0");
+    if (n_total > 0 && !xyz) return fail(LC_ERR_INVALID, "xyz is NULL");
+    if (cell_units < 0) return fail(LC_ERR_INVALID, "cell_units < 0");
+    if (cat_offsets[0] != 0) return fail(LC_ERR_INVALID, "cat_offsets[0] != 0");
+    for (int32_t c = 0; c < n_cat; c++)
+        if (cat_offsets[c + 1] < cat_offsets[c])
+            return fail(LC_ERR_INVALID, "cat_offsets decreasing at %d", c);
+    if (cat_offsets[n_cat] != n_total) return fail(LC_ERR_INVALID, "cat_offsets[n_cat] != n_total");
+    if (n_total >= (int64_t(1) << 40)) return fail(LC_ERR_OVERFLOW, "n_total too large");
+
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t rmax = b->r_edges[b->n_r];
+
+    GridGeom g{};
+    g.periodic = b->periodic;
+    g.box = b->periodic ? b->box_units : 0;
+    unsigned* d_err = nullptr;
+    LC_TRY(dev_alloc((void**)&d_err, 64, s));
+    k_zero_u32<<<1, 64, 0, s>>>(d_err, 16);
+    if (b->periodic) {
+        for (int a = 0; a < 3; a++) {
+            g.lo[a] = 0;
+            g.ext[a] = b->box_units;
+        }
+    } else {
+        int32_t* d_box = (int32_t*)(d_err + 8);
+        k_fill_box<<<1, 64, 0, s>>>(d_box);
+        if (n_total > 0)
+            k_bbox<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_box, d_err);
+        unsigned h[16];
+        LC_TRY_HIP(hipMemcpyAsync(h, d_err, sizeof h, hipMemcpyDeviceToHost, s));
+        LC_TRY_HIP(hipStreamSynchronize(s));
+        if (h[0] & 1u) {
+            dev_free(d_err, s);
+            return fail(LC_ERR_RANGE, "a coordinate is outside |x| < 2^24");
+        }
+        const int32_t* hb = (const int32_t*)(h + 8);
+        for (int a = 0; a < 3; a++) {
+            if (n_total == 0) {
+                g.lo[a] = 0;
+                g.ext[a] = 1;
+            } else {
+                g.lo[a] = hb[a];
+                g.ext[a] = int64_t(hb[3 + a]) - hb[a] + 1;
+            }
+        }
+    }
+
+    // cell side: requested, or about 96 points per cell of a mean catalogue,
+    // kept within [r_max / 3, r_max]
+    double vol = double(g.ext[0]) * double(g.ext[1]) * double(g.ext[2]);
+    double w;
+    if (cell_units > 0) {
+        w = cell_units;
+    } else {
+        double nbar = std::max(1.0, double(n_total) / n_cat);
+        w = std::cbrt(vol * 96.0 / nbar);
+        w = std::min(std::max(w, double(rmax) / 3.0), double(rmax));
+    }
+    w = std::max(w, 1.0);
+    for (;;) {
+        g.ncell = 1;
+        for (int a = 0; a < 3; a++) {
+            int64_t na = int64_t(std::floor(double(g.ext[a]) / w));
+            na = std::max<int64_t>(1, std::min<int64_t>(na, 1024));
+            g.n[a] = int32_t(na);
+            g.ncell *= na;
+        }
+        if (g.ncell * int64_t(n_cat) <= (int64_t(1) << 28)) break;
+        w *= 1.25;
+    }
+
+    auto* cells = new lc_cells();
+    cells->device = ctx->device;
+    cells->n_cat = n_cat;
+    cells->n_total = n_total;
+    cells->offsets.assign(cat_offsets, cat_offsets + n_cat + 1);
+    cells->g = g;
+    cells->los = b->los;
+    cells->r_max = rmax;
+    const int64_t ntot_cells = g.ncell * int64_t(n_cat);
+    size_t pts_bytes = size_t(std::max<int64_t>(n_total, 1)) * sizeof(double4);
+    size_t cs_bytes = size_t(ntot_cells + 1) * sizeof(int64_t);
+    if (hipMalloc(&cells->pts, pts_bytes) != hipSuccess ||
+        hipMalloc(&cells->cs, cs_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        free_cells_mem(cells);
+        delete cells;
+        dev_free(d_err, s);
+        return fail(LC_ERR_NOMEM, "mesh allocation (%zu + %zu bytes) failed", pts_bytes, cs_bytes);
+    }
+    cells->bytes = pts_bytes + cs_bytes;
+
+    // temporaries
+    int64_t* d_off = nullptr;
+    int64_t* d_gid = nullptr;
+    unsigned* d_cnt = nullptr;
+    int64_t* d_bsum = nullptr;
+    const int64_t nblk = (ntot_cells + kScanTile - 1) / kScanTile;
+    lc_status st = LC_OK;
+    {
+        Stager stg(ctx);
+        stg.push(cat_offsets, sizeof(int64_t) * (n_cat + 1));
+        st = stg.commit(s, (void**)&d_off);
+    }
+    if (st == LC_OK) st = dev_alloc((void**)&d_gid, sizeof(int64_t) * std::max<int64_t>(n_total, 1), s);
+    if (st == LC_OK) st = dev_alloc((void**)&d_cnt, sizeof(unsigned) * ntot_cells, s);
+    if (st == LC_OK) st = dev_alloc((void**)&d_bsum, sizeof(int64_t) * (nblk + 1), s);
+    if (st != LC_OK) {
+        dev_free(d_off, s);
+        dev_free(d_gid, s);
+        dev_free(d_cnt, s);
+        dev_free(d_bsum, s);
+        dev_free(d_err, s);
+        lc_free_cells(cells);
+        return st;
+    }
+    k_zero_u32<<<grid_for(ntot_cells, 256, ctx->n_cu), 256, 0, s>>>(d_cnt, ntot_cells);
+    if (n_total > 0)
+        k_cell_count<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_off, n_cat, g,
+                                                                       d_gid, d_cnt, d_err);
+    k_scan_reduce<<<nblk, kScanThreads, 0, s>>>(d_cnt, ntot_cells, d_bsum);
+    k_scan_top<<<1, kScanThreads, 0, s>>>(d_bsum, nblk, d_bsum + nblk);
+    k_scan_down<<<nblk, kScanThreads, 0, s>>>(d_cnt, ntot_cells, d_bsum, cells->cs);
+    k_scan_last<<<1, 1, 0, s>>>(cells->cs, ntot_cells, d_bsum + nblk);
+    if (n_total > 0)
+        k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, d_cnt,
+                                                                    cells->pts);
+    unsigned herr = 0;
+    hipError_t e = hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s);
+    dev_free(d_off, s);
+    dev_free(d_gid, s);
+    dev_free(d_cnt, s);
+    dev_free(d_bsum, s);
+    dev_free(d_err, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        lc_free_cells(cells);
+        return fail(LC_ERR_HIP, "mesh build failed: %s", hipGetErrorString(e));
+    }
+    if (herr & 2u) {
+        lc_free_cells(cells);
+        return fail(LC_ERR_RANGE, "a coordinate is outside the periodic box [0, %d)", g.box);
+    }
+    *out = cells;
+    return LC_OK;
+}

@@ -1,0 +1,700 @@
+// Sample covariances over mocks and the linear construction (Sect. 2.2, 2.3),
+// plus the positive-definiteness check of the result (Sect. 3).
+//
+//   mean (float64, two passes)  ->  deviations  ->  Cov_e = D_e^T D_e / (N-1)
+//   for the three estimates e = (D,R1), (D,R2), (D,R1uR2)
+//   ->  C^a = (Cov_0 + Cov_1)/2, C^b = Cov_2, A = 2C^b - C^a,
+//       B = 2 M_a (C^a - C^b), C = A + B/M            (float64)
+//   ->  Cholesky and eigenvalue extremes of each block of C (float64).
+//
+// The products D^T D run either in float64 (VALU) or as float32 MFMA
+// (v_mfma_f32_32x32x2f32) with float32 accumulation over chunks of 256
+// mocks whose partial sums are added in float64.
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <vector>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------
+// mean and deviations
+// ---------------------------------------------------------------------------
+constexpr int kMeanRows = 64;
+
+// partial[c][j] = sum of xi[n][j] over rows n of chunk c (j < 3P)
+__global__ void k_mean_partial(const double* __restrict__ xi, int64_t n_mock, int64_t W3,
+                               double* __restrict__ partial) {
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= W3) return;
+    const int64_t n0 = int64_t(blockIdx.y) * kMeanRows;
+    const int64_t n1 = min(n0 + kMeanRows, n_mock);
+    double s = 0.0;
+    for (int64_t n = n0; n < n1; n++) s += xi[n * W3 + j];
+    partial[int64_t(blockIdx.y) * W3 + j] = s;
+}
+
+__global__ void k_mean_final(const double* __restrict__ partial, int64_t nchunk, int64_t W3, int64_t n_mock,
+                             double* __restrict__ mean) {
+    const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (j >= W3) return;
+    double s = 0.0;
+    for (int64_t c = 0; c < nchunk; c++) s += partial[c * W3 + j];
+    mean[j] = s / double(n_mock);
+}
+
+// dev64[e][n][p] = xi[n][e][p] - mean[e][p]    (ld = P)
+__global__ void k_dev64(const double* __restrict__ xi, const double* __restrict__ mean, int64_t n_mock,
+                        int64_t P, double* __restrict__ dev) {
+    const int64_t tot = 3 * n_mock * P;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t p = t % P;
+        const int64_t r = t / P;
+        const int64_t n = r % n_mock;
+        const int64_t e = r / n_mock;
+        dev[t] = xi[n * 3 * P + e * P + p] - mean[e * P + p];
+    }
+}
+
+// dev32[e][n][p] (ld = Ppad, Npad rows, zero padded) = float(xi - mean)
+__global__ void k_dev32(const double* __restrict__ xi, const double* __restrict__ mean, int64_t n_mock,
+                        int64_t P, int64_t Npad, int64_t Ppad, float* __restrict__ dev) {
+    const int64_t tot = 3 * Npad * Ppad;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t p = t % Ppad;
+        const int64_t r = t / Ppad;
+        const int64_t n = r % Npad;
+        const int64_t e = r / Npad;
+        float v = 0.0f;
+        if (n < n_mock && p < P) v = float(xi[n * 3 * P + e * P + p] - mean[e * P + p]);
+        dev[t] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SYRK, float64: 64x64 tiles, 16x16 threads with 4x4 outputs each
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void tri_tile(int t, int& ti, int& tj) {
+    // t enumerates (ti, tj) with tj <= ti
+    ti = int((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ti++;
+    while (ti * (ti + 1) / 2 > t) ti--;
+    tj = t - ti * (ti + 1) / 2;
+}
+
+__global__ __launch_bounds__(256) void k_syrk64(const double* __restrict__ dev, int64_t n_mock, int64_t P,
+                                                double denom, double* __restrict__ cov) {
+    __shared__ double As[16][64 + 1];
+    __shared__ double Bs[16][64 + 1];
+    const int e = blockIdx.y;
+    int ti, tj;
+    tri_tile(blockIdx.x, ti, tj);
+    const int64_t i0 = int64_t(ti) * 64, j0 = int64_t(tj) * 64;
+    const double* D = dev + int64_t(e) * n_mock * P;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    double acc[4][4] = {};
+    for (int64_t n0 = 0; n0 < n_mock; n0 += 16) {
+        for (int q = threadIdx.x; q < 16 * 64; q += 256) {
+            const int kk = q >> 6, c = q & 63;
+            const int64_t n = n0 + kk;
+            As[kk][c] = (n < n_mock && i0 + c < P) ? D[n * P + i0 + c] : 0.0;
+            Bs[kk][c] = (n < n_mock && j0 + c < P) ? D[n * P + j0 + c] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 16; kk++) {
+            double a[4], b[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                a[r] = As[kk][ty * 4 + r];
+                b[r] = Bs[kk][tx * 4 + r];
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++)
+#pragma unroll
+                for (int c = 0; c < 4; c++) acc[r][c] = fma(a[r], b[c], acc[r][c]);
+        }
+        __syncthreads();
+    }
+    double* C = cov + int64_t(e) * P * P;
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            const int64_t i = i0 + ty * 4 + r, j = j0 + tx * 4 + c;
+            if (i < P && j < P) {
+                const double v = acc[r][c] / denom;
+                C[i * P + j] = v;
+                if (ti != tj) C[j * P + i] = v;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// SYRK, float32 MFMA: 128x128 tile per block, 2x2 waves of 64x64,
+// each wave 2x2 blocks of v_mfma_f32_32x32x2f32.
+// Operand layout of the 32x32x2 instruction (wave64): lane l supplies
+// A[i = l%32][k = l/32] and B[k = l/32][j = l%32]; accumulator register r of
+// lane l holds D[i = 8*(r/4) + 4*(l/32) + r%4][j = l%32].
+// ---------------------------------------------------------------------------
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kMT = 128;    // tile
+constexpr int kKT = 32;     // rows per LDS slab
+constexpr int kKC = 256;    // rows per float32 accumulation chunk
+
+__global__ __launch_bounds__(256) void k_syrk32(const float* __restrict__ dev, int64_t Npad, int64_t Ppad,
+                                                int64_t P, double denom, double* __restrict__ cov) {
+    __shared__ __align__(16) float As[kKT][kMT];
+    __shared__ __align__(16) float Bs[kKT][kMT];
+    const int e = blockIdx.y;
+    int ti, tj;
+    tri_tile(blockIdx.x, ti, tj);
+    const int64_t i0 = int64_t(ti) * kMT, j0 = int64_t(tj) * kMT;
+    const float* D = dev + int64_t(e) * Npad * Ppad;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wr = wid >> 1, wc = wid & 1;
+    const int li = lane & 31, lk = lane >> 5;
+    f32x16 acc[2][2];
+    double dacc[2][2][16];
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++) {
+            for (int r = 0; r < 16; r++) {
+                acc[a][b][r] = 0.0f;
+                dacc[a][b][r] = 0.0;
+            }
+        }
+    int64_t since = 0;
+    for (int64_t n0 = 0; n0 < Npad; n0 += kKT) {
+        // each thread loads 4 float4 of each slab: 32 rows x 128 floats
+        for (int q = threadIdx.x; q < kKT * kMT / 4; q += 256) {
+            const int kk = q / (kMT / 4), c4 = (q % (kMT / 4)) * 4;
+            const float4 va = *reinterpret_cast<const float4*>(D + (n0 + kk) * Ppad + i0 + c4);
+            const float4 vb = *reinterpret_cast<const float4*>(D + (n0 + kk) * Ppad + j0 + c4);
+            *reinterpret_cast<float4*>(&As[kk][c4]) = va;
+            *reinterpret_cast<float4*>(&Bs[kk][c4]) = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < kKT; ks += 2) {
+            float a0 = As[ks + lk][wr * 64 + li];
+            float a1 = As[ks + lk][wr * 64 + 32 + li];
+            float b0 = Bs[ks + lk][wc * 64 + li];
+            float b1 = Bs[ks + lk][wc * 64 + 32 + li];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+        since += kKT;
+        if (since == kKC || n0 + kKT >= Npad) {
+            for (int a = 0; a < 2; a++)
+                for (int b = 0; b < 2; b++)
+                    for (int r = 0; r < 16; r++) {
+                        dacc[a][b][r] += double(acc[a][b][r]);
+                        acc[a][b][r] = 0.0f;
+                    }
+            since = 0;
+        }
+    }
+    double* C = cov + int64_t(e) * P * P;
+    for (int a = 0; a < 2; a++)
+        for (int b = 0; b < 2; b++)
+            for (int r = 0; r < 16; r++) {
+                const int64_t i = i0 + wr * 64 + a * 32 + 8 * (r >> 2) + 4 * lk + (r & 3);
+                const int64_t j = j0 + wc * 64 + b * 32 + li;
+                if (i < P && j < P) {
+                    const double v = dacc[a][b][r] / denom;
+                    C[i * P + j] = v;
+                    if (ti != tj) C[j * P + i] = v;
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// linear construction (float64)
+// ---------------------------------------------------------------------------
+__global__ void k_combine(const double* __restrict__ cov, int64_t PP, double two_ma, double M, int m_inf,
+                          double* __restrict__ A, double* __restrict__ B, double* __restrict__ C) {
+#pragma clang fp contract(off)
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < PP;
+         t += int64_t(gridDim.x) * blockDim.x) {
+        const double ca = 0.5 * (cov[t] + cov[PP + t]);
+        const double cb = cov[2 * PP + t];
+        const double a = 2.0 * cb - ca;
+        const double b = two_ma * (ca - cb);
+        A[t] = a;
+        B[t] = b;
+        C[t] = m_inf ? a : a + b / M;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Frobenius norms for the float32-vs-float64 report
+// ---------------------------------------------------------------------------
+__global__ void k_frob(const double* __restrict__ x, const double* __restrict__ y, int64_t n,
+                       double* __restrict__ part) {
+    __shared__ double sd[256], sy[256];
+    double d = 0.0, s = 0.0;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+        const double df = x[t] - y[t];
+        d += df * df;
+        s += y[t] * y[t];
+    }
+    sd[threadIdx.x] = d;
+    sy[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            sd[threadIdx.x] += sd[threadIdx.x + o];
+            sy[threadIdx.x] += sy[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sd[0];
+        part[2 * blockIdx.x + 1] = sy[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// check: copy a diagonal block, Cholesky, Householder tridiagonalisation,
+// bisection on the tridiagonal for the extreme eigenvalues and the number of
+// negative ones.  Work matrix: n x n row-major, ld = n.
+// ---------------------------------------------------------------------------
+struct CheckFlags {
+    int nan_seen;
+    int chol_fail;
+};
+
+__global__ void k_copy_block(const double* __restrict__ C, int64_t P, int64_t off, int64_t n,
+                             double* __restrict__ W, CheckFlags* fl) {
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n * n; t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = t / n, j = t % n;
+        const double v = C[(off + i) * P + off + j];
+        W[t] = v;
+        if (v != v) fl->nan_seen = 1;
+    }
+}
+
+__global__ void k_zero_flags(CheckFlags* fl, int n) {
+    if (int(threadIdx.x) < n) {
+        fl[threadIdx.x].nan_seen = 0;
+        fl[threadIdx.x].chol_fail = 0;
+    }
+}
+
+constexpr int kNB = 32;
+
+// factor the diagonal block [k0, k0+nb) in place (lower triangle)
+__global__ void k_potrf_diag(double* __restrict__ W, int64_t n, int64_t k0, int nb, CheckFlags* fl) {
+    __shared__ double L[kNB][kNB + 1];
+    __shared__ int bad;
+    if (fl->chol_fail || fl->nan_seen) return;
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) L[t / nb][t % nb] = W[(k0 + t / nb) * n + k0 + t % nb];
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    for (int j = 0; j < nb; j++) {
+        if (threadIdx.x == 0) {
+            double d = L[j][j];
+            for (int q = 0; q < j; q++) d -= L[j][q] * L[j][q];
+            if (!(d > 0.0)) bad = 1;
+            L[j][j] = bad ? 1.0 : sqrt(d);
+        }
+        __syncthreads();
+        if (bad) break;
+        for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) {
+            double v = L[i][j];
+            for (int q = 0; q < j; q++) v -= L[i][q] * L[j][q];
+            L[i][j] = v / L[j][j];
+        }
+        __syncthreads();
+    }
+    if (bad) {
+        if (threadIdx.x == 0) fl->chol_fail = 1;
+        return;
+    }
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+        const int i = t / nb, j = t % nb;
+        if (j <= i) W[(k0 + i) * n + k0 + j] = L[i][j];
+    }
+}
+
+// rows below the diagonal block: L21 = A21 L11^{-T}, one thread per row
+__global__ void k_potrf_panel(double* __restrict__ W, int64_t n, int64_t k0, int nb, const CheckFlags* fl) {
+    __shared__ double L[kNB][kNB + 1];
+    if (fl->chol_fail || fl->nan_seen) return;
+    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) L[t / nb][t % nb] = W[(k0 + t / nb) * n + k0 + t % nb];
+    __syncthreads();
+    const int64_t i = k0 + nb + blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    double x[kNB];
+    for (int j = 0; j < nb; j++) {
+        double v = W[i * n + k0 + j];
+        for (int q = 0; q < j; q++) v -= x[q] * L[j][q];
+        x[j] = v / L[j][j];
+    }
+    for (int j = 0; j < nb; j++) W[i * n + k0 + j] = x[j];
+}
+
+// trailing update of the lower triangle: A22 -= L21 L21^T
+__global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ W, int64_t n, int64_t k0, int nb,
+                                                      const CheckFlags* fl) {
+    if (fl->chol_fail || fl->nan_seen) return;
+    __shared__ double Ai[64][kNB + 1];
+    __shared__ double Aj[64][kNB + 1];
+    const int64_t base = k0 + nb;
+    int ti, tj;
+    tri_tile(blockIdx.x, ti, tj);
+    const int64_t i0 = base + int64_t(ti) * 64, j0 = base + int64_t(tj) * 64;
+    for (int t = threadIdx.x; t < 64 * nb; t += 256) {
+        const int r = t / nb, q = t % nb;
+        Ai[r][q] = (i0 + r < n) ? W[(i0 + r) * n + k0 + q] : 0.0;
+        Aj[r][q] = (j0 + r < n) ? W[(j0 + r) * n + k0 + q] : 0.0;
+    }
+    __syncthreads();
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    for (int r = 0; r < 4; r++)
+        for (int c = 0; c < 4; c++) {
+            const int ir = ty * 4 + r, jc = tx * 4 + c;
+            const int64_t i = i0 + ir, j = j0 + jc;
+            if (i < n && j < n && j <= i) {
+                double s = 0.0;
+                for (int q = 0; q < nb; q++) s += Ai[ir][q] * Aj[jc][q];
+                W[i * n + j] -= s;
+            }
+        }
+}
+
+// Householder step k: v from row k (= column k of the symmetric trailing
+// matrix), tau, d[k], e[k].
+__global__ void k_hh_vec(const double* __restrict__ W, int64_t n, int64_t k, double* __restrict__ v,
+                         double* __restrict__ tau, double* __restrict__ d, double* __restrict__ e) {
+    __shared__ double red[256];
+    const int64_t m = n - k - 1;
+    const double* row = W + k * n + k + 1;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += row[i] * row[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double norm2 = red[0];
+    const double x0 = row[0];
+    const double nrm = sqrt(norm2);
+    const double alpha = x0 > 0 ? -nrm : nrm;   // reflect x onto alpha * e1
+    const double v0 = x0 - alpha;
+    const double vnorm2 = norm2 - x0 * x0 + v0 * v0;
+    const bool trivial = !(vnorm2 > 0.0) || (norm2 - x0 * x0) <= 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v[i] = trivial ? 0.0 : (i == 0 ? v0 : row[i]);
+    if (threadIdx.x == 0) {
+        d[k] = W[k * n + k];
+        e[k] = trivial ? x0 : alpha;
+        *tau = trivial ? 0.0 : 2.0 / vnorm2;
+    }
+}
+
+// p = tau * A22 v, one wave per row of the trailing matrix
+__global__ void k_hh_matvec(const double* __restrict__ W, int64_t n, int64_t k, const double* __restrict__ v,
+                            const double* __restrict__ tau, double* __restrict__ pv) {
+    const int64_t m = n - k - 1;
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) >> 6;
+    if (r >= m) return;
+    const double* row = W + (k + 1 + r) * n + k + 1;
+    double s = 0.0;
+    for (int64_t j = lane; j < m; j += 64) s += row[j] * v[j];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    if (lane == 0) pv[r] = *tau * s;
+}
+
+// w = p - (tau/2)(v.p) v
+__global__ void k_hh_w(int64_t m, const double* __restrict__ v, const double* __restrict__ tau,
+                       const double* __restrict__ pv, double* __restrict__ w) {
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += v[i] * pv[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double K = 0.5 * *tau * red[0];
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) w[i] = pv[i] - K * v[i];
+}
+
+// A22 -= v w^T + w v^T
+__global__ void k_hh_update(double* __restrict__ W, int64_t n, int64_t k, const double* __restrict__ v,
+                            const double* __restrict__ w) {
+    const int64_t m = n - k - 1;
+    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < m * m; t += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = t / m, j = t % m;
+        W[(k + 1 + i) * n + k + 1 + j] -= v[i] * w[j] + w[i] * v[j];
+    }
+}
+
+__global__ void k_hh_tail(const double* __restrict__ W, int64_t n, double* __restrict__ d, double* __restrict__ e) {
+    if (threadIdx.x != 0) return;
+    if (n >= 2) {
+        d[n - 2] = W[(n - 2) * n + n - 2];
+        e[n - 2] = W[(n - 1) * n + n - 2];
+    }
+    d[n - 1] = W[(n - 1) * n + n - 1];
+}
+
+// number of eigenvalues of the tridiagonal (d, e) below x (Sturm count)
+__device__ int sturm_count(const double* d, const double* e, int64_t n, double x, double pivmin) {
+    int c = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) c++;
+    for (int64_t i = 1; i < n; i++) {
+        q = d[i] - x - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0) c++;
+    }
+    return c;
+}
+
+// out: [0] min eig, [1] max eig, [2] count below 0 (as double)
+__global__ void k_bisect(const double* __restrict__ d, const double* __restrict__ e, int64_t n,
+                         const CheckFlags* fl, double* __restrict__ out) {
+    __shared__ double lo_s, hi_s, piv_s;
+    __shared__ int cnt[256];
+    if (fl->nan_seen) {
+        if (threadIdx.x == 0) {
+            out[0] = out[1] = __builtin_nan("");
+            out[2] = -1.0;
+        }
+        return;
+    }
+    double glo = 0, ghi = 0, emax2 = 0;
+    if (threadIdx.x == 0) {
+        glo = DBL_MAX;
+        ghi = -DBL_MAX;
+        for (int64_t i = 0; i < n; i++) {
+            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+            glo = fmin(glo, d[i] - r);
+            ghi = fmax(ghi, d[i] + r);
+            if (i + 1 < n) emax2 = fmax(emax2, e[i] * e[i]);
+        }
+        const double span = fmax(fabs(glo), fabs(ghi));
+        glo -= 2.0 * DBL_EPSILON * span * n + DBL_MIN;
+        ghi += 2.0 * DBL_EPSILON * span * n + DBL_MIN;
+        lo_s = glo;
+        hi_s = ghi;
+        piv_s = DBL_MIN * fmax(1.0, emax2);
+    }
+    __syncthreads();
+    const double pivmin = piv_s;
+    for (int which = 0; which < 2; which++) {
+        // which 0: smallest x with count(x) >= 1; which 1: smallest x with count(x) >= n
+        double lo = lo_s, hi = hi_s;
+        const int target = which == 0 ? 1 : int(n);
+        for (int it = 0; it < 12; it++) {
+            const double x = lo + (hi - lo) * double(threadIdx.x + 1) / double(blockDim.x + 1);
+            cnt[threadIdx.x] = sturm_count(d, e, n, x, pivmin);
+            __syncthreads();
+            // bracket: largest point with count < target, smallest with count >= target
+            double nlo = lo, nhi = hi;
+            for (int q = 0; q < int(blockDim.x); q++) {
+                const double xq = lo + (hi - lo) * double(q + 1) / double(blockDim.x + 1);
+                if (cnt[q] < target) nlo = xq;
+                else {
+                    nhi = xq;
+                    break;
+                }
+            }
+            __syncthreads();
+            lo = nlo;
+            hi = nhi;
+            if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
+        }
+        if (threadIdx.x == 0) out[which] = 0.5 * (lo + hi);
+    }
+    if (threadIdx.x == 0) out[2] = double(sturm_count(d, e, n, 0.0, pivmin));
+}
+
+static int nblocks(int64_t n, int threads, int cap = 4096) {
+    return int(std::max<int64_t>(1, std::min<int64_t>((n + threads - 1) / threads, cap)));
+}
+
+// Check one diagonal block [off, off+n) of C.  Writes chol_ok, n_neg, min, max.
+static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n, hipStream_t s,
+                             int32_t* chol_ok, int32_t* n_neg, double* mn, double* mx) {
+    double* W = nullptr;
+    double* aux = nullptr;
+    CheckFlags* fl = nullptr;
+    LC_TRY(dev_alloc((void**)&W, sizeof(double) * n * n, s));
+    const int64_t naux = 5 * n + 16;
+    LC_TRY(dev_alloc((void**)&aux, sizeof(double) * naux, s));
+    LC_TRY(dev_alloc((void**)&fl, sizeof(CheckFlags) * 2, s));
+    k_zero_flags<<<1, 64, 0, s>>>(fl, 2);
+    double* v = aux;
+    double* pv = aux + n;
+    double* w = aux + 2 * n;
+    double* d = aux + 3 * n;
+    double* e = aux + 4 * n;
+    double* tau = aux + 5 * n;
+    double* res = aux + 5 * n + 4;
+    // Cholesky
+    k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl);
+    for (int64_t k0 = 0; k0 < n; k0 += kNB) {
+        const int nb = int(std::min<int64_t>(kNB, n - k0));
+        k_potrf_diag<<<1, 64, 0, s>>>(W, n, k0, nb, fl);
+        const int64_t rest = n - k0 - nb;
+        if (rest > 0) {
+            k_potrf_panel<<<nblocks(rest, 64, 1 << 20), 64, 0, s>>>(W, n, k0, nb, fl);
+            const int64_t T = (rest + 63) / 64;
+            k_potrf_update<<<int(T * (T + 1) / 2), 256, 0, s>>>(W, n, k0, nb, fl);
+        }
+    }
+    // eigenvalues: fresh copy, tridiagonalise, bisect
+    k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl + 1);
+    for (int64_t k = 0; k + 2 < n; k++) {
+        const int64_t m = n - k - 1;
+        k_hh_vec<<<1, 256, 0, s>>>(W, n, k, v, tau, d, e);
+        k_hh_matvec<<<nblocks(m * 64, 256, 1 << 20), 256, 0, s>>>(W, n, k, v, tau, pv);
+        k_hh_w<<<1, 256, 0, s>>>(m, v, tau, pv, w);
+        k_hh_update<<<nblocks(m * m, 256), 256, 0, s>>>(W, n, k, v, w);
+    }
+    k_hh_tail<<<1, 64, 0, s>>>(W, n, d, e);
+    k_bisect<<<1, 256, 0, s>>>(d, e, n, fl + 1, res);
+    CheckFlags hf[2];
+    double hr[3];
+    LC_TRY_HIP(hipMemcpyAsync(hf, fl, sizeof hf, hipMemcpyDeviceToHost, s));
+    LC_TRY_HIP(hipMemcpyAsync(hr, res, sizeof hr, hipMemcpyDeviceToHost, s));
+    dev_free(W, s);
+    dev_free(aux, s);
+    dev_free(fl, s);
+    LC_TRY_HIP(hipStreamSynchronize(s));
+    *chol_ok = (!hf[0].nan_seen && !hf[0].chol_fail) ? 1 : 0;
+    *n_neg = int32_t(hr[2]);
+    *mn = hr[0];
+    *mx = hr[1];
+    return LC_OK;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n_mu, int32_t m_a,
+                                   double M, int32_t precision, double* A, double* B, double* C,
+                                   lc_cov_report* rep, void* stream) {
+    clear_error();
+    if (!xi || !C) return fail(LC_ERR_INVALID, "xi and C must not be NULL");
+    if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
+    if (n_r < 1 || n_mu < 1 || n_mu > LC_MAX_NMU || int64_t(n_r) * n_mu > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
+    if (m_a < 1) return fail(LC_ERR_INVALID, "m_a = %d, must be >= 1", m_a);
+    if (!(M > 0.0)) return fail(LC_ERR_INVALID, "M must be > 0 (or INFINITY)");
+    if (precision != LC_FP64 && precision != LC_FP32_MFMA && precision != LC_FP32_MFMA_CHECKED)
+        return fail(LC_ERR_INVALID, "precision = %d is not LC_FP64 / LC_FP32_MFMA / LC_FP32_MFMA_CHECKED",
+                    precision);
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = n_mock;
+    const int64_t P = int64_t(n_r) * n_mu + 3 * int64_t(n_r);
+    const int64_t PP = P * P;
+    const int64_t W3 = 3 * P;
+    const double denom = double(N - 1);
+    const int m_inf = std::isinf(M) ? 1 : 0;
+
+    double* mean = nullptr;
+    double* part = nullptr;
+    double* cov = nullptr;
+    double* Aw = A;
+    double* Bw = B;
+    LC_TRY(dev_alloc((void**)&mean, sizeof(double) * W3, s));
+    const int64_t nchunk = (N + kMeanRows - 1) / kMeanRows;
+    LC_TRY(dev_alloc((void**)&part, sizeof(double) * W3 * nchunk, s));
+    LC_TRY(dev_alloc((void**)&cov, sizeof(double) * 3 * PP, s));
+    if (!Aw) LC_TRY(dev_alloc((void**)&Aw, sizeof(double) * PP, s));
+    if (!Bw) LC_TRY(dev_alloc((void**)&Bw, sizeof(double) * PP, s));
+    {
+        dim3 g(unsigned((W3 + 255) / 256), unsigned(nchunk));
+        k_mean_partial<<<g, 256, 0, s>>>(xi, N, W3, part);
+        k_mean_final<<<unsigned((W3 + 255) / 256), 256, 0, s>>>(part, nchunk, W3, N, mean);
+    }
+    const int64_t T64 = (P + 63) / 64;
+    auto run_fp64 = [&](double* covbuf) -> lc_status {
+        double* dev = nullptr;
+        LC_TRY(dev_alloc((void**)&dev, sizeof(double) * 3 * N * P, s));
+        k_dev64<<<nblocks(3 * N * P, 256, 65536), 256, 0, s>>>(xi, mean, N, P, dev);
+        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 3), 256, 0, s>>>(dev, N, P, denom, covbuf);
+        dev_free(dev, s);
+        return LC_OK;
+    };
+    auto run_fp32 = [&](double* covbuf) -> lc_status {
+        const int64_t Npad = (N + kKT - 1) / kKT * kKT;
+        const int64_t Ppad = (P + kMT - 1) / kMT * kMT;
+        float* dev = nullptr;
+        LC_TRY(dev_alloc((void**)&dev, sizeof(float) * 3 * Npad * Ppad, s));
+        k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, Npad, Ppad, dev);
+        const int64_t T = Ppad / kMT;
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev, Npad, Ppad, P, denom, covbuf);
+        dev_free(dev, s);
+        return LC_OK;
+    };
+    const double two_ma = 2.0 * double(m_a);
+    if (precision == LC_FP64) {
+        LC_TRY(run_fp64(cov));
+    } else {
+        LC_TRY(run_fp32(cov));
+    }
+    k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, two_ma, M, m_inf, Aw, Bw, C);
+    double rel[3] = {-1.0, -1.0, -1.0};
+    if (precision == LC_FP32_MFMA_CHECKED) {
+        double *A64 = nullptr, *B64 = nullptr, *C64 = nullptr, *fpart = nullptr;
+        LC_TRY(dev_alloc((void**)&A64, sizeof(double) * PP, s));
+        LC_TRY(dev_alloc((void**)&B64, sizeof(double) * PP, s));
+        LC_TRY(dev_alloc((void**)&C64, sizeof(double) * PP, s));
+        const int nfb = 512;
+        LC_TRY(dev_alloc((void**)&fpart, sizeof(double) * 2 * nfb * 3, s));
+        LC_TRY(run_fp64(cov));
+        k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, two_ma, M, m_inf, A64, B64, C64);
+        k_frob<<<nfb, 256, 0, s>>>(C, C64, PP, fpart);
+        k_frob<<<nfb, 256, 0, s>>>(Aw, A64, PP, fpart + 2 * nfb);
+        k_frob<<<nfb, 256, 0, s>>>(Bw, B64, PP, fpart + 4 * nfb);
+        std::vector<double> h(2 * nfb * 3);
+        LC_TRY_HIP(hipMemcpyAsync(h.data(), fpart, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        dev_free(A64, s);
+        dev_free(B64, s);
+        dev_free(C64, s);
+        dev_free(fpart, s);
+        LC_TRY_HIP(hipStreamSynchronize(s));
+        for (int q = 0; q < 3; q++) {
+            double num = 0, den = 0;
+            for (int bkt = 0; bkt < nfb; bkt++) {
+                num += h[q * 2 * nfb + 2 * bkt];
+                den += h[q * 2 * nfb + 2 * bkt + 1];
+            }
+            rel[q] = den > 0 ? std::sqrt(num / den) : (num > 0 ? INFINITY : 0.0);
+        }
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(LC_ERR_HIP, "covariance launch failed: %s", hipGetErrorString(e));
+    dev_free(mean, s);
+    dev_free(part, s);
+    dev_free(cov, s);
+    if (rep) {
+        rep->rel_frob_vs_fp64[0] = rel[0];
+        rep->rel_frob_vs_fp64[1] = rel[1];
+        rep->rel_frob_vs_fp64[2] = rel[2];
+        const int64_t nb0 = int64_t(n_r) * n_mu;
+        LC_TRY(check_block(C, P, 0, nb0, s, &rep->chol_ok[0], &rep->n_neg_eig[0], &rep->min_eig[0],
+                           &rep->max_eig[0]));
+        LC_TRY(check_block(C, P, nb0, 3 * int64_t(n_r), s, &rep->chol_ok[1], &rep->n_neg_eig[1],
+                           &rep->min_eig[1], &rep->max_eig[1]));
+    }
+    if (!A) dev_free(Aw, s);
+    if (!B) dev_free(Bw, s);
+    return LC_OK;
+}

@@ -1,0 +1,114 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lc.h"
+
+namespace lc {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+lc_status fail(lc_status code, const char* fmt, ...);
+
+#define LC_TRY_HIP(call)                                                                  \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ::lc::fail(LC_ERR_HIP, "%s failed: %s (%s:%d)", #call,                 \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                 \
+    } while (0)
+
+#define LC_TRY(expr)                                                                      \
+    do {                                                                                  \
+        lc_status s_ = (expr);                                                            \
+        if (s_ != LC_OK) return s_;                                                       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// per-device context
+// ---------------------------------------------------------------------------
+struct DeviceCtx {
+    int device = -1;
+    int n_cu = 0;
+    size_t max_lds_block = 65536;
+    std::mutex mu;
+    // pinned staging for small host->device parameter copies; guarded by an
+    // event so the host never overwrites bytes a pending copy still reads
+    void* pinned = nullptr;
+    size_t pinned_size = 0;
+    hipEvent_t pinned_ev = nullptr;
+    bool pinned_pending = false;
+};
+
+// Context of the current device (created on first use).
+lc_status get_ctx(DeviceCtx** out);
+
+// Stages host arrays into one pinned block and copies them to a
+// stream-ordered device allocation with a single hipMemcpyAsync.
+class Stager {
+  public:
+    explicit Stager(DeviceCtx* c) : ctx_(c) {}
+    // reserve space for `bytes` from `src`; returns the offset in the block
+    size_t push(const void* src, size_t bytes);
+    // allocate the device block on `s`, copy, record the guard event.
+    lc_status commit(hipStream_t s, void** dev_base);
+
+  private:
+    DeviceCtx* ctx_;
+    std::vector<unsigned char> host_;
+};
+
+// Stream-ordered device allocation (hipMallocAsync / hipFreeAsync on the
+// device's default pool, whose release threshold is raised at set-up).
+lc_status dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// geometry shared by the mesh and the pair kernels
+// ---------------------------------------------------------------------------
+struct GridGeom {
+    int32_t n[3];        // cells per axis
+    int32_t lo[3];       // origin, coordinate units
+    int64_t ext[3];      // extent per axis: periodic = box, open = hi - lo + 1
+    int32_t periodic;
+    int32_t box;
+    int64_t ncell;       // n[0] * n[1] * n[2]
+};
+
+}  // namespace lc
+
+// Opaque mesh handle (public name from lc.h).
+struct lc_cells {
+    int device = -1;
+    int32_t n_cat = 0;
+    int64_t n_total = 0;
+    std::vector<int64_t> offsets;   // host copy [n_cat + 1]
+    lc::GridGeom g{};
+    int32_t los = 0;
+    int64_t r_max = 0;              // largest r edge the mesh was built for
+    double4* pts = nullptr;         // sorted points (x, y, z, 0) as float64
+    int64_t* cs = nullptr;          // cell starts [n_cat * ncell + 1], global point index
+    size_t bytes = 0;
+};
+
+namespace lc {
+// Validates a binning (see lc.h); LC_OK or LC_ERR_INVALID / LC_ERR_RANGE.
+lc_status check_binning(const lc_binning* b);
+
+// Number of stencil offsets and the list itself for a mesh and r_max.
+// Order: [0] = (0,0,0); then the lexicographically positive half; then the
+// negative half.  Offsets whose cells cannot hold a pair closer than r_max
+// are pruned.  Returns n_half (self + positive half).
+int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out);
+}  // namespace lc

@@ -1,0 +1,255 @@
+"""ctypes binding of liblc.so (include/lc.h): argument marshalling only.
+
+Every computation runs in the HIP library; this module converts arguments
+(torch device tensors -> device pointers, numpy arrays -> host pointers,
+torch streams -> hipStream_t) and turns status codes into exceptions.
+The library must be built (``python -m paper_2205_11852_amd.build``); there is
+no fallback path: a missing library raises ``LcLibraryMissing``.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblc.so")
+
+LC_OK, LC_ERR_INVALID, LC_ERR_RANGE, LC_ERR_OVERFLOW, LC_ERR_HIP, LC_ERR_NOMEM = 0, -1, -2, -3, -4, -5
+LC_LOS_Z, LC_LOS_MID = 0, 1
+LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
+LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED = 0, 1, 2
+LC_MAX_BINS, LC_MAX_NMU = 8192, 1024
+
+STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ERR_OVERFLOW",
+                -4: "LC_ERR_HIP", -5: "LC_ERR_NOMEM"}
+
+# the exported symbols of include/lc.h
+EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
+           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_release_caches"]
+
+
+class LcLibraryMissing(RuntimeError):
+    pass
+
+
+class LcError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+class lc_binning(ctypes.Structure):
+    _fields_ = [("periodic", ctypes.c_int32), ("box_units", ctypes.c_int32), ("los", ctypes.c_int32),
+                ("n_r", ctypes.c_int32), ("r_edges", ctypes.POINTER(ctypes.c_int32)),
+                ("n_mu", ctypes.c_int32)]
+
+
+class lc_task(ctypes.Structure):
+    _fields_ = [("cat_a", ctypes.c_int32), ("cat_b", ctypes.c_int32)]
+
+
+class lc_tuning(ctypes.Structure):
+    _fields_ = [("cells_per_item", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class lc_cells_info(ctypes.Structure):
+    _fields_ = [("n_cat", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
+                ("cell_side", ctypes.c_double * 3), ("n_total", ctypes.c_int64),
+                ("bytes", ctypes.c_int64)]
+
+
+class lc_cov_report(ctypes.Structure):
+    _fields_ = [("chol_ok", ctypes.c_int32 * 2), ("n_neg_eig", ctypes.c_int32 * 2),
+                ("min_eig", ctypes.c_double * 2), ("max_eig", ctypes.c_double * 2),
+                ("rel_frob_vs_fp64", ctypes.c_double * 3)]
+
+    def as_dict(self):
+        return {"chol_ok": list(self.chol_ok), "n_neg_eig": list(self.n_neg_eig),
+                "min_eig": list(self.min_eig), "max_eig": list(self.max_eig),
+                "rel_frob_vs_fp64": list(self.rel_frob_vs_fp64)}
+
+
+_lib = None
+
+
+def lib():
+    """Load liblc.so (raises LcLibraryMissing if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise LcLibraryMissing("%s is not built; run python -m paper_2205_11852_amd.build" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, st = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32
+    L.lc_last_error.restype = ctypes.c_char_p
+    L.lc_last_error.argtypes = []
+    L.lc_build_cells.restype = st
+    L.lc_build_cells.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning), i32, vp,
+                                 ctypes.POINTER(vp)]
+    L.lc_free_cells.restype = None
+    L.lc_free_cells.argtypes = [vp]
+    L.lc_cells_get_info.restype = st
+    L.lc_cells_get_info.argtypes = [vp, ctypes.POINTER(lc_cells_info)]
+    L.lc_pair_count_batch.restype = st
+    L.lc_pair_count_batch.argtypes = [vp, vp, i32, ctypes.POINTER(lc_binning), vp, i32,
+                                      ctypes.POINTER(lc_tuning), vp, vp]
+    L.lc_xi_multipoles.restype = st
+    L.lc_xi_multipoles.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, vp, vp]
+    L.lc_covariance.restype = st
+    L.lc_covariance.argtypes = [vp, i32, i32, i32, i32, ctypes.c_double, i32, vp, vp, vp,
+                                ctypes.POINTER(lc_cov_report), vp]
+    L.lc_release_caches.restype = None
+    L.lc_release_caches.argtypes = []
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().lc_last_error().decode()
+
+
+def _check(status: int):
+    if status != LC_OK:
+        raise LcError(status, last_error())
+
+
+# ---------------------------------------------------------------------------
+# marshalling helpers
+# ---------------------------------------------------------------------------
+
+def _dptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None / a raw int)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return int(t.data_ptr())
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return int(torch.cuda.current_stream().cuda_stream)
+        except Exception:
+            pass
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Binning:
+    """Owns the host edge array that lc_binning points at."""
+
+    def __init__(self, r_edges: Sequence[int], n_mu: int, periodic: bool, box_units: int = 0,
+                 los: int = LC_LOS_Z):
+        self.edges = np.ascontiguousarray(np.asarray(r_edges, dtype=np.int32))
+        self.n_r = len(self.edges) - 1
+        self.n_mu = int(n_mu)
+        self.c = lc_binning(int(bool(periodic)), int(box_units), int(los), int(self.n_r),
+                            self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_mu))
+
+    @property
+    def P(self) -> int:
+        return self.n_r * self.n_mu + 3 * self.n_r
+
+    @classmethod
+    def from_workload(cls, wl) -> "Binning":
+        return cls(wl.r_edges_units, wl.n_mu, wl.periodic, wl.box_units,
+                   LC_LOS_MID if wl.los == "mid" else LC_LOS_Z)
+
+
+def tasks_array(tasks) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(tasks, dtype=np.int32).reshape(-1, 2))
+    return t
+
+
+# ---------------------------------------------------------------------------
+# C-ABI calls
+# ---------------------------------------------------------------------------
+
+class Cells:
+    """lc_cells handle; freed on close() / garbage collection."""
+
+    def __init__(self, handle: int):
+        self.handle = handle
+
+    def info(self) -> dict:
+        inf = lc_cells_info()
+        _check(lib().lc_cells_get_info(self.handle, ctypes.byref(inf)))
+        return {"n_cat": inf.n_cat, "grid": list(inf.grid), "cell_side": list(inf.cell_side),
+                "n_total": inf.n_total, "bytes": inf.bytes}
+
+    def close(self):
+        if self.handle:
+            lib().lc_free_cells(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def lc_build_cells(xyz, cat_offsets, binning: Binning, cell_units: int = 0, stream=None) -> Cells:
+    """xyz: int32 device tensor [3, n_total]; cat_offsets: int64 [n_cat+1]."""
+    off = np.ascontiguousarray(np.asarray(cat_offsets, dtype=np.int64))
+    n_total = int(off[-1]) if len(off) else 0
+    if xyz is not None and not isinstance(xyz, int):
+        if tuple(xyz.shape) != (3, n_total) or str(xyz.dtype) != "torch.int32" or not xyz.is_contiguous():
+            raise ValueError("xyz must be a contiguous int32 tensor of shape (3, %d)" % n_total)
+    out = ctypes.c_void_p()
+    _check(lib().lc_build_cells(_dptr(xyz), n_total, off.ctypes.data, len(off) - 1,
+                                ctypes.byref(binning.c), int(cell_units), _stream(stream),
+                                ctypes.byref(out)))
+    return Cells(out.value)
+
+
+def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int = LC_PERSISTENT,
+                        tune: Optional[dict] = None, stats=None, stream=None):
+    """counts: uint64-as-int64 device tensor [n_tasks, n_r, n_mu], added into."""
+    t = tasks_array(tasks)
+    if counts is not None and not isinstance(counts, int):
+        if counts.numel() != len(t) * binning.n_r * binning.n_mu or counts.element_size() != 8:
+            raise ValueError("counts must hold n_tasks * n_r * n_mu 64-bit integers")
+    tn = None
+    if tune:
+        tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
+                       int(tune.get("blocks_per_cu", 0)), 0)
+    _check(lib().lc_pair_count_batch(cells.handle if cells else None, t.ctypes.data, len(t),
+                                     ctypes.byref(binning.c), _dptr(counts), int(mode),
+                                     ctypes.byref(tn) if tn is not None else None, _dptr(stats),
+                                     _stream(stream)))
+
+
+def lc_xi_multipoles(counts, tasks, cat_sizes, est, n_r: int, n_mu: int, xi, stream=None):
+    t = tasks_array(tasks)
+    sz = np.ascontiguousarray(np.asarray(cat_sizes, dtype=np.int64))
+    e = np.ascontiguousarray(np.asarray(est, dtype=np.int32).reshape(-1, 5))
+    _check(lib().lc_xi_multipoles(_dptr(counts), t.ctypes.data, len(t), sz.ctypes.data, len(sz),
+                                  e.ctypes.data, len(e), int(n_r), int(n_mu), _dptr(xi),
+                                  _stream(stream)))
+
+
+def lc_covariance(xi, n_mock: int, n_r: int, n_mu: int, m_a: int, M: float, precision: int,
+                  A, B, C, report: bool = True, stream=None) -> Optional[dict]:
+    rep = lc_cov_report() if report else None
+    _check(lib().lc_covariance(_dptr(xi), int(n_mock), int(n_r), int(n_mu), int(m_a), float(M),
+                               int(precision), _dptr(A), _dptr(B), _dptr(C),
+                               ctypes.byref(rep) if rep is not None else None, _stream(stream)))
+    return rep.as_dict() if rep is not None else None
+
+
+def lc_release_caches():
+    lib().lc_release_caches()
+
+
+INF = math.inf

@@ -1,0 +1,135 @@
+"""Host orchestration of the LC path: task planning and the ordered C-ABI calls.
+
+The paper's procedure (Sect. 2.3, 4.4): for every mock D with random
+catalogues R1 and R2 count DD, DR1, DR2, RR1, RR2 (RR of a shared random
+sub-catalogue is counted once), form xi(D,R1), xi(D,R2) and the split
+xi(D, R1 u R2), then the covariances and the linear construction.  All
+arithmetic happens in liblc.so; this module only builds the task table and
+moves arguments.
+"""
+from __future__ import annotations
+
+import time
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import lc
+
+
+def plan_tasks(n_mock: int, randoms: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Task table (cat_a, cat_b) and, per mock, the task ids of DD, DR1, DR2,
+    RR1, RR2.  RR of a sub-catalogue shared by several mocks appears once."""
+    tasks: List[Tuple[int, int]] = []
+    index: Dict[Tuple[int, int], int] = {}
+
+    def tid(a: int, b: int) -> int:
+        key = (int(a), int(b))
+        if key not in index:
+            index[key] = len(tasks)
+            tasks.append(key)
+        return index[key]
+
+    est = np.zeros((n_mock, 5), dtype=np.int32)
+    for m in range(n_mock):
+        r1, r2 = int(randoms[m, 0]), int(randoms[m, 1])
+        est[m] = (tid(m, m), tid(m, r1), tid(m, r2), tid(r1, r1), tid(r2, r2))
+    return np.array(tasks, dtype=np.int32).reshape(-1, 2), est
+
+
+class Pipeline:
+    """Device-resident catalogues of one workload and the calls of the path."""
+
+    def __init__(self, cats, device: str = "cuda", M: float = 50.0, m_a: int = 1):
+        import torch
+        self.torch = torch
+        self.cats = cats
+        self.wl = cats.wl
+        self.device = device
+        self.binning = lc.Binning.from_workload(self.wl)
+        self.tasks, self.est = plan_tasks(cats.n_mock, cats.randoms)
+        self.sizes = cats.sizes()
+        self.offsets = cats.offsets
+        self.M = float(M)
+        self.m_a = int(m_a)
+        self.xyz = torch.from_numpy(cats.xyz).to(device)
+        self.n_mock = cats.n_mock
+        nb = self.binning.n_r * self.binning.n_mu
+        P = self.binning.P
+        self.counts = torch.zeros((len(self.tasks), self.binning.n_r, self.binning.n_mu),
+                                  dtype=torch.int64, device=device)
+        self.stats = torch.zeros(4, dtype=torch.int64, device=device)
+        self.xi = torch.empty((self.n_mock, 3, P), dtype=torch.float64, device=device)
+        self.A = torch.empty((P, P), dtype=torch.float64, device=device)
+        self.B = torch.empty((P, P), dtype=torch.float64, device=device)
+        self.C = torch.empty((P, P), dtype=torch.float64, device=device)
+        self.cells: Optional[lc.Cells] = None
+        self._nb = nb
+
+    # -- steps ---------------------------------------------------------------
+    def build_cells(self, cell_units: int = 0):
+        if self.cells is not None:
+            self.cells.close()
+        self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units)
+        return self.cells
+
+    def count(self, mode: int = lc.LC_PERSISTENT, tune: Optional[dict] = None, zero: bool = True):
+        if zero:
+            self.counts.zero_()
+            self.stats.zero_()
+        lc.lc_pair_count_batch(self.cells, self.tasks, self.binning, self.counts, mode, tune,
+                               self.stats)
+
+    def count_per_mock(self, tune: Optional[dict] = None, sync: bool = True):
+        """Baseline: one launch per task, mock after mock, synchronising after
+        each mock (shared RR counted once, before the loop)."""
+        torch = self.torch
+        self.counts.zero_()
+        self.stats.zero_()
+        nbytes = self._nb * 8
+        base = int(self.counts.data_ptr())
+        sbase = int(self.stats.data_ptr())
+        done = set()
+
+        def one(t):
+            lc.lc_pair_count_batch(self.cells, self.tasks[t:t + 1], self.binning, base + t * nbytes,
+                                   lc.LC_PER_TASK, tune, sbase)
+
+        for t in sorted(set(int(v) for v in self.est[:, 3:].ravel())):
+            one(t)
+            done.add(t)
+        if sync:
+            torch.cuda.synchronize()
+        for m in range(self.n_mock):
+            for t in self.est[m, :3]:
+                if int(t) not in done:
+                    one(int(t))
+                    done.add(int(t))
+            if sync:
+                torch.cuda.synchronize()
+
+    def xi_multipoles(self):
+        b = self.binning
+        lc.lc_xi_multipoles(self.counts, self.tasks, self.sizes, self.est, b.n_r, b.n_mu, self.xi)
+
+    def covariance(self, precision: int = lc.LC_FP32_MFMA, report: bool = True, M: Optional[float] = None):
+        b = self.binning
+        return lc.lc_covariance(self.xi, self.n_mock, b.n_r, b.n_mu, self.m_a,
+                                self.M if M is None else M, precision, self.A, self.B, self.C, report)
+
+    def run(self, mode: int = lc.LC_PERSISTENT, precision: int = lc.LC_FP32_MFMA, report: bool = True,
+            cell_units: int = 0, tune: Optional[dict] = None) -> dict:
+        """The whole path on device-resident catalogues; returns the check report."""
+        self.build_cells(cell_units)
+        self.count(mode, tune)
+        self.xi_multipoles()
+        return self.covariance(precision, report)
+
+    # -- host copies ---------------------------------------------------------
+    def counts_host(self) -> np.ndarray:
+        return self.counts.cpu().numpy().view(np.uint64)
+
+    def stats_host(self) -> Dict[str, int]:
+        s = self.stats.cpu().numpy().view(np.uint64)
+        return {"candidates": int(s[0]), "binned": int(s[1]), "exact_fallback": int(s[2]),
+                "flushes": int(s[3])}

@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol
+declared in include/lc.h, and rejects bad arguments with the documented
+status before any HIP call."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2205_11852_amd import lc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "lc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(lc.LIB_PATH):
+        from paper_2205_11852_amd import build
+        build.build()
+    return lc.lib()
+
+
+def test_exports_match_header(L):
+    declared = _header_functions()
+    assert set(declared) == set(lc.EXPORTS), declared
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_no_fallback_when_library_missing(monkeypatch, tmp_path):
+    monkeypatch.setattr(lc, "_lib", None)
+    monkeypatch.setattr(lc, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(lc.LcLibraryMissing):
+        lc.lib()
+
+
+def _binning(**kw):
+    d = dict(r_edges=[0, 10, 20, 30], n_mu=4, periodic=True, box_units=1000, los=lc.LC_LOS_Z)
+    d.update(kw)
+    return lc.Binning(**d)
+
+
+def _build_status(L, b, n_total=4, offsets=(0, 4), out=True, xyz=0x1000):
+    off = np.array(offsets, dtype=np.int64)
+    h = ctypes.c_void_p()
+    return L.lc_build_cells(xyz, n_total, off.ctypes.data, len(off) - 1, ctypes.byref(b.c), 0, None,
+                            ctypes.byref(h) if out else None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(r_edges=[0, 20, 10]), lc.LC_ERR_INVALID),          # not increasing
+    (dict(r_edges=[-1, 10]), lc.LC_ERR_INVALID),             # negative edge
+    (dict(n_mu=0), lc.LC_ERR_INVALID),
+    (dict(n_mu=lc.LC_MAX_NMU + 1), lc.LC_ERR_INVALID),
+    (dict(r_edges=list(range(0, 2 * 4097, 2)), n_mu=3), lc.LC_ERR_INVALID),   # too many bins
+    (dict(r_edges=[0, 10, 500]), lc.LC_ERR_RANGE),           # r_max >= box/2
+    (dict(box_units=999), lc.LC_ERR_INVALID),                # odd box
+    (dict(box_units=(1 << 24) + 2), lc.LC_ERR_INVALID),
+    (dict(los=lc.LC_LOS_MID), lc.LC_ERR_INVALID),            # midpoint needs open geometry
+    (dict(los=7, periodic=False), lc.LC_ERR_INVALID),
+    (dict(periodic=False, r_edges=[0, 1 << 25]), lc.LC_ERR_RANGE),
+])
+def test_build_cells_rejects_bad_binning(L, kw, code):
+    assert _build_status(L, _binning(**kw)) == code
+    assert lc.last_error()
+
+
+def test_build_cells_rejects_bad_layout(L):
+    b = _binning()
+    assert _build_status(L, b, out=False) == lc.LC_ERR_INVALID
+    assert _build_status(L, b, offsets=(1, 4)) == lc.LC_ERR_INVALID         # [0] != 0
+    assert _build_status(L, b, offsets=(0, 3, 2, 4)) == lc.LC_ERR_INVALID   # decreasing
+    assert _build_status(L, b, n_total=5) == lc.LC_ERR_INVALID              # last != n_total
+    assert _build_status(L, b, xyz=0) == lc.LC_ERR_INVALID                  # NULL points
+    assert "xyz" in lc.last_error()
+
+
+def test_pair_count_rejects_bad_arguments(L):
+    b = _binning()
+    t = np.array([[0, 0]], dtype=np.int32)
+    st = L.lc_pair_count_batch(None, t.ctypes.data, 1, ctypes.byref(b.c), 0x1000, 0, None, None, None)
+    assert st == lc.LC_ERR_INVALID and "cells" in lc.last_error()
+
+
+def test_xi_rejects_inconsistent_tasks(L):
+    tasks = np.array([[0, 0], [0, 1], [0, 2], [1, 1], [2, 2]], dtype=np.int32)
+    sizes = np.array([10, 10, 10], dtype=np.int64)
+    good = np.array([[0, 1, 2, 3, 4]], dtype=np.int32)
+    bad_order = np.array([[1, 0, 2, 3, 4]], dtype=np.int32)
+    bad_id = np.array([[0, 1, 2, 3, 9]], dtype=np.int32)
+    for est in (bad_order, bad_id):
+        st = L.lc_xi_multipoles(0x1000, tasks.ctypes.data, 5, sizes.ctypes.data, 3, est.ctypes.data, 1,
+                                3, 4, 0x2000, None)
+        assert st == lc.LC_ERR_INVALID
+    tiny = np.array([1, 10, 10], dtype=np.int64)
+    st = L.lc_xi_multipoles(0x1000, tasks.ctypes.data, 5, tiny.ctypes.data, 3, good.ctypes.data, 1, 3, 4,
+                            0x2000, None)
+    assert st == lc.LC_ERR_INVALID and ">= 2" in lc.last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(n_mock=1), lc.LC_ERR_INVALID),
+    (dict(m_a=0), lc.LC_ERR_INVALID),
+    (dict(M=0.0), lc.LC_ERR_INVALID),
+    (dict(M=float("nan")), lc.LC_ERR_INVALID),
+    (dict(precision=9), lc.LC_ERR_INVALID),
+    (dict(n_mu=0), lc.LC_ERR_INVALID),
+    (dict(C=0), lc.LC_ERR_INVALID),
+])
+def test_covariance_rejects_bad_arguments(L, args, code):
+    a = dict(xi=0x1000, n_mock=10, n_r=3, n_mu=4, m_a=1, M=50.0, precision=lc.LC_FP64, A=0, B=0, C=0x2000)
+    a.update(args)
+    st = L.lc_covariance(a["xi"], a["n_mock"], a["n_r"], a["n_mu"], a["m_a"], a["M"], a["precision"],
+                         a["A"], a["B"], a["C"], None, None)
+    assert st == code
+
+
+def test_last_error_is_thread_local_string(L):
+    assert isinstance(lc.last_error(), str)

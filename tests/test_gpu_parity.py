@@ -1,0 +1,315 @@
+"""GPU path vs the CPU oracle, through the C ABI.
+
+Counts are compared bit for bit; xi and multipoles in float64 to 1e-12
+relative to the magnitude of the terms summed; covariances from the float64
+path to 1e-12 and from the float32-MFMA path to 1e-5 relative Frobenius.
+"""
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+import mockgen
+from tests.fixtures import edge_pairs, two_point_catalogues
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.fail("GPU tests need a visible GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def lcmod(torch):
+    from paper_2205_11852_amd import lc
+    lc.lib()  # raises if the library is not built
+    return lc
+
+
+@pytest.fixture(scope="module")
+def c1(torch, lcmod, oracle_mod):
+    from paper_2205_11852_amd.pipeline import Pipeline
+    _say("[c1] generating")
+    cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"])
+    pl = Pipeline(cats)
+    pl.build_cells()
+    pl.count()
+    torch.cuda.synchronize()
+    gpu = pl.counts_host().copy()
+    wl = cats.wl
+    _say("[c1] oracle counts for %d tasks" % len(pl.tasks))
+    ref = np.zeros_like(gpu)
+    for t, (a, b) in enumerate(pl.tasks):
+        ref[t] = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units,
+                                        wl.n_mu, wl.box_units, wl.los)
+    return dict(pl=pl, cats=cats, gpu=gpu, ref=ref)
+
+
+def test_c1_counts_bit_exact(c1):
+    assert np.array_equal(c1["gpu"], c1["ref"])
+    st = c1["pl"].stats_host()
+    assert st["binned"] == int(c1["ref"].sum())
+    assert st["candidates"] >= st["binned"]
+
+
+@pytest.mark.parametrize("mode_name", ["per_task", "graph", "graph_per_task", "force_exact"])
+def test_c1_modes_identical(c1, lcmod, torch, mode_name):
+    pl = c1["pl"]
+    mode = {"per_task": lcmod.LC_PER_TASK, "graph": lcmod.LC_GRAPH,
+            "graph_per_task": lcmod.LC_GRAPH | lcmod.LC_PER_TASK,
+            "force_exact": lcmod.LC_FORCE_EXACT}[mode_name]
+    reps = 3 if "graph" in mode_name else 1
+    for r in range(reps):
+        _say("[c1] mode", mode_name, "replay", r)
+        pl.count(mode)
+        torch.cuda.synchronize()
+        assert np.array_equal(pl.counts_host(), c1["ref"]), (mode_name, r)
+    if mode_name == "force_exact":
+        st = pl.stats_host()
+        assert st["exact_fallback"] == st["binned"]
+
+
+def test_c1_per_mock_baseline_identical(c1, torch):
+    pl = c1["pl"]
+    pl.count_per_mock()
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.counts_host(), c1["ref"])
+
+
+@pytest.mark.parametrize("tune", [dict(cells_per_item=1), dict(cells_per_item=7, waves_per_block=1),
+                                  dict(waves_per_block=8, blocks_per_cu=1), dict(waves_per_block=2)])
+def test_c1_tunings_identical(c1, torch, tune):
+    pl = c1["pl"]
+    _say("[c1] tune", tune)
+    pl.count(tune=tune)
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.counts_host(), c1["ref"])
+
+
+@pytest.mark.parametrize("cell_mpc", [25.0, 33.0, 50.0, 100.0, 160.0])
+def test_c1_cell_sizes_identical(c1, torch, cell_mpc):
+    pl = c1["pl"]
+    _say("[c1] cell", cell_mpc)
+    pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC))
+    pl.count()
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.counts_host(), c1["ref"]), cell_mpc
+    pl.build_cells()
+
+
+def test_edge_pairs_gpu(torch, lcmod):
+    """Hand-derived bins of pairs exactly on r and mu edges (tests/golden)."""
+    for scale in (1, 4096, 2 ** 18 // 5):
+        for row in edge_pairs():
+            a, b, edges, box = two_point_catalogues(row, scale=scale)
+            xyz = np.concatenate([a, b], axis=1)
+            los = lcmod.LC_LOS_MID if row["los"] == "mid" else lcmod.LC_LOS_Z
+            bn = lcmod.Binning(edges, row["n_mu"], box > 0, box, los)
+            t = torch.from_numpy(np.ascontiguousarray(xyz)).cuda()
+            cells = lcmod.lc_build_cells(t, [0, 1, 2], bn)
+            counts = torch.zeros((3, bn.n_r, bn.n_mu), dtype=torch.int64, device="cuda")
+            for mode in (lcmod.LC_PERSISTENT, lcmod.LC_FORCE_EXACT):
+                counts.zero_()
+                lcmod.lc_pair_count_batch(cells, [[0, 1], [1, 0], [0, 0]], bn, counts, mode)
+                got = counts.cpu().numpy()
+                exp = np.zeros((bn.n_r, bn.n_mu), dtype=np.int64)
+                if row["k"] >= 0:
+                    exp[row["k"], row["m"]] = 1
+                assert np.array_equal(got[0], exp), (row["note"], scale, mode)
+                assert np.array_equal(got[1], exp), (row["note"], scale, mode, "swapped")
+                assert got[2].sum() == 0
+            cells.close()
+
+
+def test_xi_multipoles_parity(c1, oracle_mod, torch):
+    pl = c1["pl"]
+    pl.count()
+    pl.xi_multipoles()
+    torch.cuda.synchronize()
+    xi = pl.xi.cpu().numpy()
+    counts = c1["ref"]
+    sizes = pl.sizes
+    wl = c1["cats"].wl
+    W = oracle_mod.legendre_weights(wl.n_mu)
+    nb = wl.n_r * wl.n_mu
+    for m in range(pl.n_mock):
+        e = pl.est[m]
+        D, R1, R2 = pl.tasks[e[0]][0], pl.tasks[e[1]][1], pl.tasks[e[2]][1]
+        V = oracle_mod.mock_vectors(*(counts[t] for t in e), sizes[D], sizes[R1], sizes[R2])
+        g = xi[m]
+        nan_g, nan_r = np.isnan(g), np.isnan(V)
+        assert np.array_equal(nan_g, nan_r)
+        ok = ~nan_r
+        # xi(r, mu): same operations in the same order
+        assert np.allclose(g[:, :nb][ok[:, :nb]], V[:, :nb][ok[:, :nb]], rtol=1e-12, atol=0)
+        # multipoles: tolerance relative to the sum of |W xi| entering each one
+        for q in range(3):
+            x2 = V[q, :nb].reshape(wl.n_r, wl.n_mu)
+            scale = np.abs(x2)[:, None, :] * np.abs(W)[None, :, :]
+            scale = scale.sum(axis=2).T.ravel()
+            d = np.abs(g[q, nb:] - V[q, nb:])
+            fin = np.isfinite(V[q, nb:])
+            assert np.all(d[fin] <= 1e-12 * scale[fin] + 1e-300)
+
+
+@pytest.fixture(scope="module")
+def c1_cov(c1, oracle_mod, torch):
+    pl = c1["pl"]
+    pl.count()
+    pl.xi_multipoles()
+    torch.cuda.synchronize()
+    xi = pl.xi.cpu().numpy()
+    A, B, C, Ca, Cb = oracle_mod.lc_from_vectors(xi, 1, 50.0)
+    return dict(xi=xi, A=A, B=B, C=C)
+
+
+def _rel_frob(x, y):
+    m = np.isfinite(y)
+    return np.linalg.norm((x - y)[m]) / np.linalg.norm(y[m])
+
+
+def test_covariance_fp64_parity(c1, c1_cov, lcmod, torch):
+    pl = c1["pl"]
+    for M in (50.0, 1.0, 2.0, float("inf")):
+        pl.covariance(lcmod.LC_FP64, report=False, M=M)
+        torch.cuda.synchronize()
+        A, B, C = (t.cpu().numpy() for t in (pl.A, pl.B, pl.C))
+        exp_C = c1_cov["A"] if np.isinf(M) else c1_cov["A"] + c1_cov["B"] / M
+        assert np.array_equal(np.isnan(C), np.isnan(exp_C))
+        assert _rel_frob(A, c1_cov["A"]) < 1e-12
+        assert _rel_frob(B, c1_cov["B"]) < 1e-12
+        assert _rel_frob(C, exp_C) < 1e-12, M
+        assert np.array_equal(C[np.isfinite(C)], C.T[np.isfinite(C)])
+
+
+def test_covariance_fp32_mfma_parity(c1, c1_cov, lcmod, torch):
+    pl = c1["pl"]
+    rep = pl.covariance(lcmod.LC_FP32_MFMA_CHECKED, report=True)
+    torch.cuda.synchronize()
+    A, B, C = (t.cpu().numpy() for t in (pl.A, pl.B, pl.C))
+    assert _rel_frob(C, c1_cov["C"]) < 1e-5
+    assert _rel_frob(A, c1_cov["A"]) < 1e-5
+    assert _rel_frob(B, c1_cov["B"]) < 1e-5
+    for q in range(3):
+        assert 0 <= rep["rel_frob_vs_fp64"][q] < 1e-5, rep
+
+
+def _synthetic_vectors(n_mock, P, seed):
+    """Float64 data vectors with a smooth correlation structure (input to the
+    covariance stage only)."""
+    r = np.random.default_rng(seed)
+    L = r.normal(size=(P, P)) / np.sqrt(P) + np.eye(P)
+    base = r.normal(size=(n_mock, P)) @ L.T
+    V = np.stack([base + 0.3 * r.normal(size=(n_mock, P)) for _ in range(3)], axis=1)
+    return V
+
+
+@pytest.mark.parametrize("n_mock,n_r,n_mu", [(50, 4, 5), (300, 6, 10), (1000, 10, 20), (257, 3, 41)])
+def test_covariance_synthetic_parity_and_check(lcmod, oracle_mod, torch, n_mock, n_r, n_mu):
+    """Covariance stage on its own, at sizes that span several tiles with a
+    ragged tail, plus the Cholesky / eigenvalue report against LAPACK."""
+    P = n_r * n_mu + 3 * n_r
+    V = _synthetic_vectors(n_mock, P, n_mock + P)
+    xi = torch.from_numpy(V).cuda()
+    A, B, C = (torch.empty((P, P), dtype=torch.float64, device="cuda") for _ in range(3))
+    rA, rB, rC, _, _ = oracle_mod.lc_from_vectors(V, 1, 50.0)
+    for prec, tol in ((lcmod.LC_FP64, 1e-12), (lcmod.LC_FP32_MFMA, 1e-5)):
+        rep = lcmod.lc_covariance(xi, n_mock, n_r, n_mu, 1, 50.0, prec, A, B, C, report=True)
+        torch.cuda.synchronize()
+        gA, gB, gC = (t.cpu().numpy() for t in (A, B, C))
+        assert _rel_frob(gC, rC) < tol and _rel_frob(gA, rA) < tol and _rel_frob(gB, rB) < tol, prec
+        # the check runs on the matrix the device produced: compare with LAPACK on it
+        nb0 = n_r * n_mu
+        for blk, sl in enumerate((slice(0, nb0), slice(nb0, P))):
+            ref = oracle_mod.check_matrix(gC[sl, sl])
+            w = np.linalg.eigvalsh(gC[sl, sl])
+            scale = np.abs(w).max()
+            assert abs(rep["min_eig"][blk] - ref["min_eig"]) <= 1e-10 * scale, (blk, rep, ref)
+            assert abs(rep["max_eig"][blk] - ref["max_eig"]) <= 1e-10 * scale, (blk, rep, ref)
+            # counts and Cholesky agree unless an eigenvalue sits at rounding level
+            if np.min(np.abs(w)) > 1e-8 * scale:
+                assert rep["n_neg_eig"][blk] == ref["n_neg_eig"], (blk, rep, ref)
+                assert rep["chol_ok"][blk] == ref["chol_ok"], (blk, rep, ref)
+
+
+def test_covariance_nan_rows(lcmod, torch):
+    """rr = 0 gives NaN xi; NaN propagates to its rows and the report flags it."""
+    n_mock, n_r, n_mu = 20, 2, 3
+    P = n_r * n_mu + 3 * n_r
+    V = _synthetic_vectors(n_mock, P, 3)
+    V[:, :, 1] = np.nan
+    xi = torch.from_numpy(V).cuda()
+    A, B, C = (torch.empty((P, P), dtype=torch.float64, device="cuda") for _ in range(3))
+    rep = lcmod.lc_covariance(xi, n_mock, n_r, n_mu, 1, 50.0, lcmod.LC_FP64, A, B, C, report=True)
+    g = C.cpu().numpy()
+    assert np.all(np.isnan(g[1])) and np.all(np.isnan(g[:, 1]))
+    assert np.all(np.isfinite(np.delete(np.delete(g, 1, 0), 1, 1)))
+    assert rep["n_neg_eig"][0] == -1 and rep["chol_ok"][0] == 0
+
+
+def test_wedge_midpoint_bit_exact(torch, oracle_mod, lcmod):
+    """Open geometry with the midpoint line of sight (survey-like wedge)."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    wl = dataclasses.replace(mockgen.WORKLOADS["c4"], n_mock=3, n_mean=6000.0, n_parents=300,
+                             n_subsets=2, subset_size=6000)
+    cats = mockgen.make_catalogues(wl)
+    pl = Pipeline(cats)
+    for cell_mpc in (0, 60.0, 200.0):
+        _say("[wedge] cell", cell_mpc)
+        pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC))
+        pl.count()
+        torch.cuda.synchronize()
+        gpu = pl.counts_host()
+        for t, (a, b) in enumerate(pl.tasks):
+            ref = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units,
+                                         wl.n_mu, 0, "mid")
+            assert np.array_equal(gpu[t], ref), (cell_mpc, t)
+
+
+def test_ragged_catalogues(torch, oracle_mod, lcmod):
+    """Empty and one-point catalogues, coincident points, points on the box
+    faces, everything in one cell, non-uniform edges with e_0 > 0."""
+    L = 1 << 16
+    r = np.random.default_rng(5)
+    cats = [np.zeros((3, 0), np.int32), np.array([[5], [6], [7]], np.int32),
+            np.repeat(np.array([[100], [200], [300]], np.int32), 5, axis=1),       # coincident
+            np.array([[0, L - 1, 0, L - 1], [0, 0, L - 1, L - 1], [L - 1, 0, 0, L - 1]], np.int32),
+            r.integers(1000, 1300, size=(3, 300)).astype(np.int32),                 # one cell
+            r.integers(0, L, size=(3, 700)).astype(np.int32)]
+    off = np.cumsum([0] + [c.shape[1] for c in cats])
+    xyz = torch.from_numpy(np.ascontiguousarray(np.concatenate(cats, axis=1))).cuda()
+    tasks = [(a, b) for a in range(len(cats)) for b in range(len(cats))]
+    for edges in ([0, 100, 900, 2000, 3000, 6000], [40, 50, 64, 1000, 1001, 4321, 9000]):
+        for n_mu in (1, 3, 10):
+            bn = lcmod.Binning(edges, n_mu, True, L, lcmod.LC_LOS_Z)
+            cells = lcmod.lc_build_cells(xyz, off, bn)
+            counts = torch.zeros((len(tasks), bn.n_r, n_mu), dtype=torch.int64, device="cuda")
+            lcmod.lc_pair_count_batch(cells, tasks, bn, counts)
+            got = counts.cpu().numpy().view(np.uint64)
+            for t, (a, b) in enumerate(tasks):
+                ref = oracle_mod.count_pairs(cats[a], None if a == b else cats[b], edges, n_mu, L, "z")
+                assert np.array_equal(got[t], ref), (edges, n_mu, a, b)
+            cells.close()
+
+
+def test_out_of_box_coordinate_is_an_error(torch, lcmod):
+    L = 1000
+    xyz = torch.tensor([[1, 2, L], [3, 4, 5], [6, 7, 8]], dtype=torch.int32, device="cuda")
+    bn = lcmod.Binning([0, 10, 20], 2, True, L)
+    with pytest.raises(lcmod.LcError) as ei:
+        lcmod.lc_build_cells(xyz, [0, 3], bn)
+    assert ei.value.status == lcmod.LC_ERR_RANGE
+    big = torch.tensor([[1 << 24], [0], [0]], dtype=torch.int32, device="cuda")
+    with pytest.raises(lcmod.LcError) as ei:
+        lcmod.lc_build_cells(big, [0, 1], lcmod.Binning([0, 10], 1, False, 0, lcmod.LC_LOS_MID))
+    assert ei.value.status == lcmod.LC_ERR_RANGE
