@@ -46,6 +46,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-mock", action="store_true")
     ap.add_argument("--cell-mpc", type=float, default=0.0)
+    ap.add_argument("--sub", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this path has no multi-GPU mode "
@@ -70,7 +71,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step(events=None):
-        pl.build_cells(cell_units)
+        pl.build_cells(cell_units, args.sub)
         if events:
             events[0].record(stream)
         pl.count()

@@ -77,6 +77,17 @@ typedef struct {
  */
 typedef struct lc_cells lc_cells;
 
+/* Mesh options; NULL or 0 fields = library defaults. */
+typedef struct {
+    int32_t cell_units;       /* coarse cell side in coordinate units (default: about
+                                 96 points per cell of a mean catalogue, kept within
+                                 [r_max / 3, r_max]); rounded so cells tile the box */
+    int32_t sub;              /* sub-cells per axis inside a coarse cell: 1, 2 or 4
+                                 (default 4); pair counting skips the sub-cells that
+                                 lie beyond r_max of each group of 64 points */
+    int32_t reserved[2];
+} lc_mesh_opts;
+
 /*
  * lc_build_cells: sort every catalogue into a shared chaining mesh.
  *   xyz          DEVICE int32 SoA [3][n_total]: x[0..n), y[0..n), z[0..n);
@@ -84,22 +95,24 @@ typedef struct lc_cells lc_cells;
  *   cat_offsets  HOST int64 [n_cat + 1]; [0] = 0, non-decreasing,
  *                [n_cat] = n_total.  Catalogue c = points [off[c], off[c+1]).
  *   b            binning the mesh will be used with (geometry, r_max).
- *   cell_units   requested cell side in coordinate units; 0 = library default
- *                (about r_max / 2).  Larger values are rounded to fit the box.
+ *   opts         HOST or NULL (defaults).
  *   out          receives the mesh; free with lc_free_cells.
- * Synchronises `stream` once, to read the device range-check word (a point
- * outside the geometry returns LC_ERR_RANGE and no mesh).
+ * Synchronises `stream` (once for a periodic box, twice for open geometry:
+ * the bounding box, then the device range-check word).  A point outside the
+ * geometry returns LC_ERR_RANGE and no mesh.
  */
 lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
-                         int32_t n_cat, const lc_binning* b, int32_t cell_units,
+                         int32_t n_cat, const lc_binning* b, const lc_mesh_opts* opts,
                          void* stream, lc_cells** out);
 void lc_free_cells(lc_cells* cells);
 
 /* Mesh facts (HOST): grid cells per axis, cell side in units, points. */
 typedef struct {
     int32_t n_cat;
-    int32_t grid[3];
+    int32_t grid[3];          /* coarse cells per axis */
     double cell_side[3];
+    int32_t sub;              /* sub-cells per axis in a coarse cell */
+    int32_t reserved;
     int64_t n_total;
     int64_t bytes;            /* device memory held by the mesh */
 } lc_cells_info;
@@ -136,9 +149,10 @@ typedef struct {
  *   counts   DEVICE uint64 [n_tasks][n_r][n_mu], ADDED INTO (zero it first).
  *   mode     LC_PERSISTENT or LC_PER_TASK, optionally | LC_GRAPH | LC_FORCE_EXACT.
  *   tune     NULL for defaults.
- *   stats    DEVICE uint64 [4] or NULL, ADDED INTO: candidate pair tests,
- *            binned pairs, pairs resolved by the integer fallback, histogram
- *            flushes.
+ *   stats    DEVICE uint64 [4] or NULL, ADDED INTO: [0] candidate pair
+ *            tests, [1] reserved (0), [2] pairs decided by the integer rule
+ *            (their float estimate was within its error bound of an edge),
+ *            [3] histogram flushes.  Binned pairs = the sum of counts.
  * Asynchronous.  Counts are exact; the result does not depend on mode,
  * tuning, or the order in which tiles run.
  */

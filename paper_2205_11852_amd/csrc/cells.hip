@@ -44,37 +44,43 @@ lc_status check_binning(const lc_binning* b) {
 }
 
 int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out) {
-    // Two cells whose indices differ by d along an axis are at least
-    // (|d| - 1) * w apart on it (w = ext / n): offsets with
-    // sum max(|d|-1, 0)^2 w^2 >= r_max^2 cannot hold a binned pair.
-    double w[3];
+    // Two cells whose indices differ by d along an axis are more than
+    // (|d| - 1) * w apart on it (w = ext / n): an offset with
+    // sum max(|d|-1, 0)^2 w^2 >= r_max^2 cannot hold a pair with r < r_max.
+    // Decided exactly: multiply through by (n_x n_y n_z)^2 in 128-bit integers.
+    typedef unsigned __int128 u128;
     int k[3];
+    u128 wt[3];  // ext_a^2 * prod_{b != a} n_b^2
+    u128 rhs = u128(uint64_t(r_max)) * uint64_t(r_max);
     for (int a = 0; a < 3; a++) {
-        w[a] = double(g.ext[a]) / double(g.n[a]);
-        k[a] = int(std::floor(double(r_max) / w[a])) + 1;
-        // beyond one full turn (periodic) or the grid (open) nothing new is reachable
-        k[a] = std::min(k[a], g.n[a]);
+        rhs *= u128(uint64_t(g.n[a])) * uint64_t(g.n[a]);
+        wt[a] = u128(uint64_t(g.ext[a])) * uint64_t(g.ext[a]);
+        for (int b = 0; b < 3; b++)
+            if (b != a) wt[a] *= u128(uint64_t(g.n[b])) * uint64_t(g.n[b]);
+        // smallest |d| with (|d| - 1) * w >= r_max, capped: one full turn of a
+        // periodic grid (or the whole open grid) reaches every cell
+        int64_t kk = (r_max * g.n[a]) / g.ext[a] + 1;
+        k[a] = int(std::min<int64_t>(kk, g.n[a]));
     }
-    const double r2 = double(r_max) * double(r_max) * (1.0 + 1e-12);
     std::vector<int4> pos, neg;
     for (int dz = -k[2]; dz <= k[2]; dz++)
         for (int dy = -k[1]; dy <= k[1]; dy++)
             for (int dx = -k[0]; dx <= k[0]; dx++) {
                 if (!dx && !dy && !dz) continue;
-                int d[3] = {dx, dy, dz};
-                double s = 0;
+                const int d[3] = {dx, dy, dz};
+                u128 s = 0;
                 for (int a = 0; a < 3; a++) {
-                    double m = std::max(std::abs(d[a]) - 1, 0) * w[a];
-                    s += m * m;
+                    const uint64_t m = uint64_t(std::max(std::abs(d[a]) - 1, 0));
+                    s += u128(m * m) * wt[a];
                 }
-                if (s >= r2) continue;
-                bool positive = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
+                if (s >= rhs) continue;
+                const bool positive = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
                 (positive ? pos : neg).push_back(make_int4(dx, dy, dz, 0));
             }
     out.clear();
     out.push_back(make_int4(0, 0, 0, 0));
     out.insert(out.end(), pos.begin(), pos.end());
-    int n_half = int(out.size());
+    const int n_half = int(out.size());
     out.insert(out.end(), neg.begin(), neg.end());
     return n_half;
 }
@@ -134,10 +140,6 @@ __device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, int
     return lo;
 }
 
-__device__ __forceinline__ int32_t axis_cell(int32_t x, int32_t lo, int64_t ext, int32_t n) {
-    return int32_t((int64_t(x - lo) * n) / ext);
-}
-
 // Cell id per point and per-cell histogram; range check for periodic boxes.
 __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
                              int32_t n_cat, GridGeom g, int64_t* __restrict__ gid,
@@ -152,11 +154,14 @@ __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const i
                 continue;
             }
         }
-        int32_t cx = axis_cell(x, g.lo[0], g.ext[0], g.n[0]);
-        int32_t cy = axis_cell(y, g.lo[1], g.ext[1], g.n[1]);
-        int32_t cz = axis_cell(z, g.lo[2], g.ext[2], g.n[2]);
+        // fine index along each axis; coarse cell = fine / sub (the floors nest)
+        const int32_t fx = axis_cell(x, g.lo[0], g.ext[0], g.n[0] * g.sub);
+        const int32_t fy = axis_cell(y, g.lo[1], g.ext[1], g.n[1] * g.sub);
+        const int32_t fz = axis_cell(z, g.lo[2], g.ext[2], g.n[2] * g.sub);
+        const int32_t cx = fx / g.sub, cy = fy / g.sub, cz = fz / g.sub;
+        const int32_t sid = ((fz - cz * g.sub) * g.sub + (fy - cy * g.sub)) * g.sub + (fx - cx * g.sub);
         int32_t c = find_cat(off, n_cat, p);
-        int64_t id = int64_t(c) * g.ncell + (int64_t(cz) * g.n[1] + cy) * g.n[0] + cx;
+        int64_t id = (int64_t(c) * g.ncell + (int64_t(cz) * g.n[1] + cy) * g.n[0] + cx) * g.nsub + sid;
         gid[p] = id;
         atomicAdd(&cnt[id], 1u);
     }
@@ -232,16 +237,21 @@ __global__ void k_scan_down(const unsigned* __restrict__ cnt, int64_t n, const i
 __global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out[n] = *grand; }
 
 // Scatter: each point takes a slot in its cell (order inside a cell is free;
-// counts never depend on it).
+// counts never depend on it) and is stored relative to the cell origin.
 __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ gid,
-                          const int64_t* __restrict__ cs, unsigned* __restrict__ cnt,
-                          double4* __restrict__ pts) {
+                          const int64_t* __restrict__ cs, unsigned* __restrict__ cnt, GridGeom g,
+                          float* __restrict__ pts) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         int64_t id = gid[p];
         if (id < 0) continue;
         unsigned r = atomicSub(&cnt[id], 1u) - 1u;
-        pts[cs[id] + r] = make_double4(double(xyz[p]), double(xyz[n + p]), double(xyz[2 * n + p]), 0.0);
+        const int64_t slot = cs[id] + r;
+        const int32_t v[3] = {xyz[p], xyz[n + p], xyz[2 * n + p]};
+        for (int a = 0; a < 3; a++) {
+            const int32_t c = axis_cell(v[a], g.lo[a], g.ext[a], g.n[a]);
+            pts[3 * slot + a] = float(int64_t(v[a]) - cell_origin(c, g.lo[a], g.ext[a], g.n[a]));
+        }
     }
 }
 
@@ -273,6 +283,8 @@ extern "C" lc_status lc_cells_get_info(const lc_cells* c, lc_cells_info* info) {
     clear_error();
     if (!c || !info) return fail(LC_ERR_INVALID, "NULL argument");
     info->n_cat = c->n_cat;
+    info->sub = c->g.sub;
+    info->reserved = 0;
     for (int a = 0; a < 3; a++) {
         info->grid[a] = c->g.n[a];
         info->cell_side[a] = double(c->g.ext[a]) / double(c->g.n[a]);
@@ -283,12 +295,15 @@ extern "C" lc_status lc_cells_get_info(const lc_cells* c, lc_cells_info* info) {
 }
 
 extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
-                                    int32_t n_cat, const lc_binning* b, int32_t cell_units,
+                                    int32_t n_cat, const lc_binning* b, const lc_mesh_opts* opts,
                                     void* stream, lc_cells** out) {
     clear_error();
     if (!out) return fail(LC_ERR_INVALID, "out is NULL");
     *out = nullptr;
     LC_TRY(check_binning(b));
+    const int32_t cell_units = opts ? opts->cell_units : 0;
+    int32_t sub = opts && opts->sub ? opts->sub : 4;
+    if (sub != 1 && sub != 2 && sub != 4) return fail(LC_ERR_INVALID, "sub = %d, must be 1, 2 or 4", sub);
     if (n_cat < 1) return fail(LC_ERR_INVALID, "n_cat = %d, must be >= 1", n_cat);
     if (!cat_offsets) return fail(LC_ERR_INVALID, "cat_offsets is NULL");
     if (n_total < 0) return fail(LC_ERR_INVALID, "n_total < 0");
@@ -364,6 +379,12 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         if (g.ncell * int64_t(n_cat) <= (int64_t(1) << 28)) break;
         w *= 1.25;
     }
+    // sub-cells: at least 1 unit wide, and at most 2^31 starts in all
+    for (int a = 0; a < 3; a++)
+        while (sub > 1 && g.ext[a] / (int64_t(g.n[a]) * sub) < 1) sub /= 2;
+    while (sub > 1 && g.ncell * int64_t(n_cat) * sub * sub * sub > (int64_t(1) << 31)) sub /= 2;
+    g.sub = sub;
+    g.nsub = sub * sub * sub;
 
     auto* cells = new lc_cells();
     cells->device = ctx->device;
@@ -373,8 +394,9 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     cells->g = g;
     cells->los = b->los;
     cells->r_max = rmax;
-    const int64_t ntot_cells = g.ncell * int64_t(n_cat);
-    size_t pts_bytes = size_t(std::max<int64_t>(n_total, 1)) * sizeof(double4);
+    const int64_t ntot_cells = g.ncell * int64_t(n_cat) * g.nsub;
+    // 4 extra points of padding: pair counting reads whole groups of four
+    size_t pts_bytes = size_t(std::max<int64_t>(n_total, 1) + 4) * 3 * sizeof(float);
     size_t cs_bytes = size_t(ntot_cells + 1) * sizeof(int64_t);
     if (hipMalloc(&cells->pts, pts_bytes) != hipSuccess ||
         hipMalloc(&cells->cs, cs_bytes) != hipSuccess) {
@@ -411,6 +433,8 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         return st;
     }
     k_zero_u32<<<grid_for(ntot_cells, 256, ctx->n_cu), 256, 0, s>>>(d_cnt, ntot_cells);
+    // the padding after the last point reads as zeros
+    k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(cells->pts) + 3 * n_total, 12);
     if (n_total > 0)
         k_cell_count<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_off, n_cat, g,
                                                                        d_gid, d_cnt, d_err);
@@ -420,7 +444,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     k_scan_last<<<1, 1, 0, s>>>(cells->cs, ntot_cells, d_bsum + nblk);
     if (n_total > 0)
         k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, d_cnt,
-                                                                    cells->pts);
+                                                                    g, cells->pts);
     unsigned herr = 0;
     hipError_t e = hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s);
     dev_free(d_off, s);

@@ -83,8 +83,22 @@ struct GridGeom {
     int64_t ext[3];      // extent per axis: periodic = box, open = hi - lo + 1
     int32_t periodic;
     int32_t box;
-    int64_t ncell;       // n[0] * n[1] * n[2]
+    int64_t ncell;       // n[0] * n[1] * n[2] coarse cells
+    int32_t sub;         // sub-cells per axis inside a coarse cell (1, 2 or 4)
+    int32_t nsub;        // sub^3
 };
+
+// Cell index along an axis: floor((x - lo) n / ext).
+__host__ __device__ inline int32_t axis_cell(int32_t x, int32_t lo, int64_t ext, int32_t n) {
+    return int32_t((int64_t(x - lo) * n) / ext);
+}
+
+// Integer origin of cell c along an axis: the smallest coordinate the cell
+// can hold, lo + ceil(c ext / n).  Points are stored relative to it, so every
+// stored coordinate lies in [0, ceil(ext / n)] and is exact in float32.
+__host__ __device__ inline int64_t cell_origin(int32_t c, int32_t lo, int64_t ext, int32_t n) {
+    return int64_t(lo) + (int64_t(c) * ext + n - 1) / n;
+}
 
 }  // namespace lc
 
@@ -97,8 +111,10 @@ struct lc_cells {
     lc::GridGeom g{};
     int32_t los = 0;
     int64_t r_max = 0;              // largest r edge the mesh was built for
-    double4* pts = nullptr;         // sorted points (x, y, z, 0) as float64
-    int64_t* cs = nullptr;          // cell starts [n_cat * ncell + 1], global point index
+    float* pts = nullptr;           // sorted points, float32 (x, y, z) relative to their cell origin
+    // starts of the sub-cells, [n_cat][ncell][nsub] + 1 (global point index);
+    // coarse cell c of catalogue k spans [cs[(k ncell + c) nsub], cs[(k ncell + c + 1) nsub])
+    int64_t* cs = nullptr;
     size_t bytes = 0;
 };
 

@@ -2,77 +2,78 @@
 // DR_i and RR_i counts of the split Landy-Szalay estimator (Sect. 2.1),
 // binned as in Sect. 4.3.
 //
-// Work decomposition: a work item is (task, run of consecutive cells of
-// catalogue a).  Items of all tasks form one queue that persistent wavefronts
-// drain with an atomic counter.  For every cell a wave takes up to 64 points
-// of catalogue a (one per lane, float64 in registers) and streams the points
-// of each neighbour cell of catalogue b through wave-uniform (scalar) loads.
+// Data: every catalogue is sorted into a shared chaining mesh; points are
+// stored as float32 (x, y, z) relative to their cell's integer origin, so
+// every stored value and every difference formed below is an integer below
+// 2^24 in magnitude and exact in float32.
 //
-// Per candidate pair (phase A, all lanes): float64 separation and squared
-// distance d2 -- exact, since coordinates are integers below 2^25 -- and the
-// r-range test.  Accepted pairs are compacted into a per-wave LDS ring
-// (ballot + mbcnt), so the binning (phase B) always runs on 64 live lanes.
-// Phase B estimates the r and mu bins in float32 and keeps the estimate only
-// when it is provably away from every bin edge (error bound derived in the
-// host code that sets eps_r / eps_m); otherwise it decides with the exact
-// integer rule (int64 squared edges, 128-bit mu cross-multiplication).
-// The bin is added to a wave-private uint32 LDS histogram that is flushed
-// with uint64 global atomics when the wave moves to another task.
+// Work decomposition: a work item is (task, run of consecutive cells of
+// catalogue a).  Items form eight queues, one per XCD (workgroup w runs on
+// XCD w mod 8), each holding a contiguous, cost-balanced range of tasks so
+// that the waves sharing an XCD's L2 share catalogues; a wave whose queue is
+// empty moves on to the next queue.  For every cell a wave takes up to 64
+// points of catalogue a (one per lane) and streams the points of each
+// neighbour cell of catalogue b through wave-uniform scalar loads.
+//
+// Phase A (every candidate, all lanes): separation and a float32 squared
+// distance, accepted against r_max with a margin larger than its rounding
+// error; accepted pairs are compacted into a per-wave LDS queue
+// (ballot + mbcnt), so phase B always runs on 64 live lanes.
+// Phase B: float32 estimates of the r and mu bins, kept only when they lie
+// farther from every bin edge than their proven error (eps_r, eps_m, derived
+// in make_plan); every other pair is decided by the integer rule (int64
+// squared distance and edges, 128-bit mu cross-multiplication), which also
+// drops pairs that phase A's margin let through.  Bins go to a wave-private
+// uint32 LDS histogram flushed with uint64 global atomics when the wave
+// moves to another task.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
-#include <memory>
-#include <tuple>
+#include <string>
 
 #include "lc_internal.hpp"
 
 namespace lc {
 
-constexpr int kQ = 128;  // entries of the per-wave compaction ring
+constexpr int kQ = 128;     // entries of the per-wave compaction queue
+constexpr int kXcd = 8;     // queues (one per XCD)
 
 struct PcParams {
-    int32_t nx, ny, nz, periodic;
+    int32_t n[3];
+    int32_t periodic;
+    int32_t lo[3];
+    int32_t single_task;
+    int64_t ext[3];
+    int64_t box;
     int64_t ncell;
-    double boxd;
+    int32_t sub, nsub;          // sub-cells per axis / per coarse cell
+    float wf[3];                // sub-cell side per axis (ext / (n sub))
+    int32_t pad1;
     int32_t nhalf, nfull;
     int32_t cells_per_item, items_per_task;
-    int64_t n_items;
-    int32_t single_task;
     int32_t n_r, n_mu, nbins;
-    int32_t hist_stride;   // uint32 words per wave histogram
-    int32_t wave_bytes;    // LDS bytes per wave
-    double emin2, emax2;
-    double e0d, ded;
-    float e0f, inv_drf, nmuf, nmu_m1_eps, eps_r, eps_m;
+    int32_t hist_stride;    // uint32 words per wave histogram
+    int32_t wave_bytes;     // LDS bytes per wave
     int32_t force_exact;
-    int32_t pad_;
+    float emax2_hi, emin2_lo;   // phase A acceptance (float32, with margin)
+    int64_t emin2, emax2;       // exact squared edges
+    int64_t e0, de;             // uniform edges: e_k = e0 + k de
+    float inv_drf, e0_over_drf, nmuf, nmu_m1_eps, eps_r, eps_m;
+    uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
 
 typedef unsigned __int128 u128;
 
-__device__ __forceinline__ uint64_t sq64(int64_t v) { return uint64_t(v) * uint64_t(v); }
-
-template <bool UNIFORM>
-__device__ __forceinline__ int exact_r(double d2, int k_est, const PcParams& p,
-                                       const double* __restrict__ e2tab) {
-    if (UNIFORM) {
-        const uint64_t D2 = uint64_t(d2);
-        const int64_t e0 = int64_t(p.e0d), de = int64_t(p.ded);
-        int k = min(max(k_est, 0), p.n_r - 1);
-        while (k > 0 && D2 < sq64(e0 + int64_t(k) * de)) --k;
-        while (k < p.n_r - 1 && D2 >= sq64(e0 + int64_t(k + 1) * de)) ++k;
-        return k;
-    } else {
-        int lo = 0, hi = p.n_r;  // e2[lo] <= d2 < e2[hi]
-        while (hi - lo > 1) {
-            int mid = (lo + hi) >> 1;
-            if (e2tab[mid] <= d2) lo = mid;
-            else hi = mid;
-        }
-        return lo;
-    }
+// A value every lane holds equally, made visible as such to the compiler so
+// that loads indexed by it become scalar loads.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(v) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
 }
+
+__device__ __forceinline__ uint64_t sq64(int64_t v) { return uint64_t(v * v); }
 
 // largest m in [0, n_mu-1] with m^2 * den <= num  (den > 0)
 __device__ __forceinline__ int exact_mu(u128 den, u128 num, int m_est, int n_mu) {
@@ -82,173 +83,275 @@ __device__ __forceinline__ int exact_mu(u128 den, u128 num, int m_est, int n_mu)
     return m;
 }
 
-// Bin of one pair.  LOS 0: a = dz.  LOS 1: a = p = s.l, b = q = l.l.
+// Integer rule (the binning of Sect. 4.3 with exact comparisons): the bin of
+// separation s (midpoint: P = s.l, Q = l.l), or -1 outside [e_0, e_n).
 template <int LOS, bool UNIFORM>
-__device__ __forceinline__ int bin_pair(double d2, double a, double b, const PcParams& p,
-                                        const double* __restrict__ e2tab, bool& used_exact) {
-    const float fd2 = float(d2);
-    const float rs = __builtin_amdgcn_rsqf(fd2);
-    float tm;
-    if (LOS == 0) {
-        tm = fabsf(float(a)) * rs * p.nmuf;
-    } else {
-        const float rq = __builtin_amdgcn_rsqf(float(b));
-        tm = fabsf(float(a)) * rs * rq * p.nmuf;
-    }
-    // clamp before converting: NaN (d2 = 0 or q = 0) becomes 0 here and
-    // fails the margin test below, which sends the pair to the integer rule
-    int m = int(fminf(fmaxf(tm, 0.0f), p.nmuf));
-    const float fm = tm - float(m);
-    bool ok = (tm >= p.nmu_m1_eps) || ((fm > p.eps_m) && (fm < 1.0f - p.eps_m));
+__device__ __forceinline__ int exact_bin(int64_t sx, int64_t sy, int64_t sz, int64_t P, uint64_t Q,
+                                         int k_est, int m_est, const PcParams& p,
+                                         const int64_t* __restrict__ e2tab) {
+    const uint64_t D2 = sq64(sx) + sq64(sy) + sq64(sz);
+    if (D2 >= uint64_t(p.emax2) || D2 < uint64_t(p.emin2)) return -1;
     int k;
     if (UNIFORM) {
-        const float r = fd2 * rs;
-        const float tr = (r - p.e0f) * p.inv_drf;
-        k = int(fminf(fmaxf(tr, 0.0f), float(p.n_r)));
-        const float fr = tr - float(k);
-        ok = ok && (fr > p.eps_r) && (fr < 1.0f - p.eps_r) && (k < p.n_r);
+        k = min(max(k_est, 0), p.n_r - 1);
+        while (k > 0 && D2 < sq64(p.e0 + int64_t(k) * p.de)) --k;
+        while (k < p.n_r - 1 && D2 >= sq64(p.e0 + int64_t(k + 1) * p.de)) ++k;
     } else {
-        k = exact_r<false>(d2, 0, p, e2tab);
-    }
-    ok = ok && !p.force_exact;
-    m = min(m, p.n_mu - 1);
-    used_exact = !ok;
-    if (!ok) {
-        if (UNIFORM) k = exact_r<true>(d2, k, p, e2tab);
-        const uint64_t D2 = uint64_t(d2);
-        const uint64_t nm2 = uint64_t(p.n_mu) * uint64_t(p.n_mu);
-        if (LOS == 0) {
-            const uint64_t AZ = uint64_t(fabs(a));
-            m = (D2 == 0) ? 0 : exact_mu(u128(D2), u128(nm2) * AZ * AZ, m, p.n_mu);
-        } else {
-            const uint64_t AP = uint64_t(fabs(a)), Q = uint64_t(b);
-            m = (D2 == 0 || Q == 0) ? 0 : exact_mu(u128(D2) * Q, u128(nm2) * AP * AP, m, p.n_mu);
+        int lo = 0, hi = p.n_r;  // e2[lo] <= D2 < e2[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (uint64_t(e2tab[mid]) <= D2) lo = mid;
+            else hi = mid;
         }
+        k = lo;
+    }
+    const uint64_t nm2 = uint64_t(p.n_mu) * uint64_t(p.n_mu);
+    int m;
+    if (LOS == 0) {
+        const uint64_t AZ = uint64_t(sz < 0 ? -sz : sz);
+        m = (D2 == 0) ? 0 : exact_mu(u128(D2), u128(nm2) * AZ * AZ, m_est, p.n_mu);
+    } else {
+        const uint64_t AP = uint64_t(P < 0 ? -P : P);
+        m = (D2 == 0 || Q == 0) ? 0 : exact_mu(u128(D2) * Q, u128(nm2) * AP * AP, m_est, p.n_mu);
     }
     return k * p.n_mu + m;
 }
 
 struct WaveState {
     unsigned* hist;
-    double2* qa;
-    double* qb;
-    uint32_t qhead, qtail;
-    uint64_t since_flush;
-    uint64_t n_cand, n_binned, n_exact, n_flush;
+    float4* qa;           // linear queue of (sx, sy, sz, d2 | i-lane), entries [0, qtail)
+    int* itab;            // midpoint: absolute coordinates of the current i points
+    uint32_t qtail;       // wave-uniform
+    uint64_t since_flush; // candidate tests since the last flush (bounds every bin)
+    uint64_t n_cand;
+    uint32_t n_exact, n_flush;
     int cur_task;
 };
 
-template <int LOS, bool UNIFORM>
-__device__ __forceinline__ void drain(WaveState& w, int lane, uint32_t n, const PcParams& p,
-                                      const double* __restrict__ e2tab) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (uint32_t(lane) < n) {
-        const uint32_t pos = (w.qhead + lane) & (kQ - 1);
-        const double2 e = w.qa[pos];
-        const double b = (LOS == 1) ? w.qb[pos] : 0.0;
-        bool ex;
-        const int bin = bin_pair<LOS, UNIFORM>(e.x, e.y, b, p, e2tab, ex);
-        __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        w.n_exact += __popcll(__ballot(ex));
-    }
-    w.qhead += n;
+__device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int LOS, bool UNIFORM>
+// Bin of one queued pair, or -1 (dropped).  The float estimates are kept only
+// when farther than eps from every edge; the clamps to >= 1 make d2 = 0 and
+// q = 0 produce estimates that fail that test, so every value stays finite.
+template <int LOS, bool UNIFORM, bool HAS_E0>
+__device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__ itab, const PcParams& p,
+                                         const int64_t* __restrict__ e2tab, bool& used_exact) {
+    float d2f, u;
+    double P = 0.0, Q = 0.0;
+    if (LOS == 0) {
+        d2f = __builtin_amdgcn_fmed3f(e.w, 1.0f, 3.0e38f);
+        u = fabsf(e.z) * __builtin_amdgcn_rsqf(d2f) * p.nmuf;
+    } else {
+        // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
+        // exact in float64 (< 2^53)
+        const int il = __float_as_int(e.w);
+        const double lx = 2.0 * double(itab[3 * il]) + double(e.x);
+        const double ly = 2.0 * double(itab[3 * il + 1]) + double(e.y);
+        const double lz = 2.0 * double(itab[3 * il + 2]) + double(e.z);
+        P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
+        Q = fma(lx, lx, fma(ly, ly, lz * lz));
+        d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
+        u = fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)) *
+            p.nmuf;
+    }
+    int m = int(u);
+    const float fm = __builtin_amdgcn_fractf(u);
+    bool ok = (u >= p.nmu_m1_eps) | ((fm > p.eps_m) & (fm < 1.0f - p.eps_m));
+    int k = 0;
+    if (UNIFORM) {
+        // eps_r also covers phase A's acceptance margin, so a pair outside
+        // [e_0, e_n) never passes this test with k outside [0, n_r)
+        const float r = d2f * __builtin_amdgcn_rsqf(d2f);
+        const float t = HAS_E0 ? fmaf(r, p.inv_drf, -p.e0_over_drf) : r * p.inv_drf;
+        k = int(t);
+        const float fr = __builtin_amdgcn_fractf(t);
+        ok = ok & (fr > p.eps_r) & (fr < 1.0f - p.eps_r);
+    } else {
+        ok = false;  // non-uniform edges: every pair takes the integer rule
+    }
+    ok = ok & (p.force_exact == 0);
+    m = min(m, p.n_mu - 1);
+    used_exact = !ok;
+    if (!ok)
+        return exact_bin<LOS, UNIFORM>(int64_t(e.x), int64_t(e.y), int64_t(e.z), int64_t(P), uint64_t(Q), k,
+                                       m, p, e2tab);
+    return k * p.n_mu + m;
+}
+
+// Bin the last n (<= 64) of the qt queued pairs, one per lane (the queue is
+// an unordered bag, so taking from its end leaves the rest in place).
+// Returns the new queue length.
+template <int LOS, bool UNIFORM, bool HAS_E0>
+__device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
+                                          const int64_t* __restrict__ e2tab) {
+    wave_sync_lds();
+    const uint32_t first = qt - n;
+    bool ex = false;
+    if (uint32_t(lane) < n) {
+        const float4 e = w.qa[first + lane];
+        const int bin = bin_entry<LOS, UNIFORM, HAS_E0>(e, w.itab, p, e2tab, ex);
+        if (bin >= 0) __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    w.n_exact += uint32_t(__popcll(__builtin_amdgcn_ballot_w64(ex)));
+    wave_sync_lds();
+    return __builtin_amdgcn_readfirstlane(first);
+}
+
+template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ void flush(WaveState& w, int lane, const PcParams& p,
-                                      const double* __restrict__ e2tab,
+                                      const int64_t* __restrict__ e2tab,
                                       unsigned long long* __restrict__ counts) {
-    const uint32_t left = w.qtail - w.qhead;
-    if (left) drain<LOS, UNIFORM>(w, lane, left, p, e2tab);
+    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, e2tab);
     unsigned long long* dst = counts + int64_t(w.cur_task) * p.nbins;
     for (int b = lane; b < p.nbins; b += 64) {
         const unsigned v = w.hist[b];
         if (v) {
-            __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             w.hist[b] = 0;
         }
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
     w.since_flush = 0;
     w.n_flush++;
 }
 
-// Stream the points j in [jb, je) of catalogue b against this lane's point.
-template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF>
-__device__ __forceinline__ void scan_range(WaveState& w, int lane, int64_t jb, int64_t je, double sx,
-                                           double sy, double sz, int64_t gi,
-                                           const double4* __restrict__ pts, const PcParams& p,
-                                           const double* __restrict__ e2tab,
-                                           unsigned long long* __restrict__ counts) {
-    for (int64_t j = jb; j < je; ++j) {
-        const double4 q = pts[j];
-        const double dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
-        const double d2 = fma(dx, dx, fma(dy, dy, dz * dz));
-        bool acc = d2 < p.emax2;
-        if (HAS_EMIN) acc = acc && (d2 >= p.emin2);
-        if (SELF) acc = acc && (j > gi);
-        double va = dz, vb = 0.0;
-        if (LOS == 1) {
-            const double lx = q.x + sx, ly = q.y + sy, lz = q.z + sz;
-            va = fma(dx, lx, fma(dy, ly, dz * lz));
-            vb = fma(lx, lx, fma(ly, ly, lz * lz));
-        }
-        const unsigned long long bal = __ballot(acc);
-        if (bal) {
+struct Cand {
+    float dx, dy, dz, d2;
+    bool acc;
+};
+
+// Separation and float32 squared distance of one candidate; accepted when
+// d2 < e_max^2 (1 + 2^-20), which holds for every pair with r < e_max since
+// the float32 sum of three exact squares is within 3 * 2^-24 of d2.
+template <bool HAS_EMIN>
+__device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi, float yi, float zi,
+                                          const PcParams& p) {
+    Cand c;
+    c.dx = xj - xi;
+    c.dy = yj - yi;
+    c.dz = zj - zi;
+    c.d2 = fmaf(c.dx, c.dx, fmaf(c.dy, c.dy, c.dz * c.dz));
+    c.acc = c.d2 < p.emax2_hi;
+    if (HAS_EMIN) c.acc = c.acc & (c.d2 >= p.emin2_lo);
+    return c;
+}
+
+// Append the accepted lanes of one candidate to the queue (length qt, kept
+// wave-uniform); bin 64 of them as soon as 64 are queued.  w4: d2
+// (plane-parallel) or the i index within the chunk (midpoint).
+template <int LOS, bool UNIFORM, bool HAS_E0>
+__device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
+                                         uint32_t qt, const PcParams& p, const int64_t* __restrict__ e2tab) {
+    qt = __builtin_amdgcn_readfirstlane(qt);
+    if (bal) {
+        if (c.acc) {
             const uint32_t rank =
                 __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-            if (acc) {
-                const uint32_t pos = (w.qtail + rank) & (kQ - 1);
-                w.qa[pos] = make_double2(d2, va);
-                if (LOS == 1) w.qb[pos] = vb;
-            }
-            const uint32_t nb = __popcll(bal);
-            w.qtail += nb;
-            w.n_binned += nb;
-            w.since_flush += nb;
-            if (w.qtail - w.qhead >= 64) drain<LOS, UNIFORM>(w, lane, 64, p, e2tab);
-            // a uint32 bin can take at most this many more pairs before a flush
-            if (w.since_flush >= 0xFFFF0000ull) flush<LOS, UNIFORM>(w, lane, p, e2tab, counts);
+            w.qa[qt + rank] = make_float4(c.dx, c.dy, c.dz, LOS == 0 ? c.d2 : w4);
         }
+        qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
+        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0>(w, lane, 64, qt, p, e2tab);
     }
+    return qt;
+}
+
+// Pending j block: each lane holds one j point (in the i cell frame) or a
+// sentinel far from every i point.
+struct JBlock {
+    int64_t idx;       // global index of the point (valid lanes)
+    float ox, oy, oz;  // frame offset of the point's cell image
+    bool self;         // point of the i cell itself (auto pairs): count only j > i
+};
+
+// Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
+// scalar loads) against the j block held one point per lane.  TAIL: some of
+// the four lie past the chunk (in the padded point array) and are replaced by
+// a far sentinel.
+template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL>
+__device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
+                                                int64_t jcmp, const float* __restrict__ q, int64_t ib, int k,
+                                                int n_i, uint32_t qt, const PcParams& p,
+                                                const int64_t* __restrict__ e2tab) {
+    float a[12];
+#pragma unroll
+    for (int t = 0; t < 12; t++) a[t] = q[t];
+    if (TAIL) {
+#pragma unroll
+        for (int u = 1; u < 4; u++)
+            if (k + u >= n_i) a[3 * u] = a[3 * u + 1] = a[3 * u + 2] = 1e18f;
+    }
+    Cand c[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+        c[u] = test_pair<HAS_EMIN>(xj, yj, zj, a[3 * u], a[3 * u + 1], a[3 * u + 2], p);
+        if (SELF) c[u].acc = c[u].acc & (jcmp > ib + k + u);
+    }
+    // ballots before any branch keep the four distance chains together
+    unsigned long long bal[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) bal[u] = __builtin_amdgcn_ballot_w64(c[u].acc);
+#pragma unroll
+    for (int u = 0; u < 4; u++)
+        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(k + u), bal[u], qt, p, e2tab);
+    return qt;
+}
+
+// Test the n_i points of the i chunk (ib .. ib + n_i - 1) against the j block.
+// The chunk's 768 bytes stay in the scalar cache while every j block of the
+// chunk sweeps them.
+template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF>
+__device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int64_t jcmp,
+                                            const float* __restrict__ pts, int64_t ib, int n_i,
+                                            const PcParams& p, const int64_t* __restrict__ e2tab) {
+    ib = uniform64(ib);
+    uint32_t qt = w.qtail;
+    int k = 0;
+    for (; k + 4 <= n_i; k += 4)
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jcmp, pts + 3 * (ib + k), ib, k,
+                                                              n_i, qt, p, e2tab);
+    if (k < n_i)
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jcmp, pts + 3 * (ib + k), ib, k,
+                                                             n_i, qt, p, e2tab);
+    w.qtail = qt;
 }
 
 template <int LOS, bool UNIFORM, bool HAS_EMIN>
 __global__ __launch_bounds__(512) void k_pair_count(
-    const double4* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
-    const int32_t* __restrict__ order, const int4* __restrict__ sten, const double* __restrict__ e2tab,
-    unsigned long long* __restrict__ counts, unsigned long long* __restrict__ stats,
-    unsigned* __restrict__ queue, PcParams p) {
+    const float* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
+    const int32_t* __restrict__ order, const int4* __restrict__ sten, const int64_t* __restrict__ e2tab,
+    const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
+    unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x & 63;
     const int wid = threadIdx.x >> 6;
     unsigned char* wb = smem + size_t(wid) * p.wave_bytes;
     WaveState w;
     w.hist = reinterpret_cast<unsigned*>(wb);
-    w.qa = reinterpret_cast<double2*>(wb + size_t(p.hist_stride) * 4);
-    w.qb = reinterpret_cast<double*>(w.qa + kQ);
-    w.qhead = w.qtail = 0;
+    w.qa = reinterpret_cast<float4*>(wb + size_t(p.hist_stride) * 4);
+    w.itab = reinterpret_cast<int*>(w.qa + kQ);
+    w.qtail = 0;
     w.since_flush = 0;
-    w.n_cand = w.n_binned = w.n_exact = w.n_flush = 0;
+    w.n_cand = 0;
+    w.n_exact = w.n_flush = 0;
     w.cur_task = -1;
     for (int b = lane; b < p.hist_stride; b += 64) w.hist[b] = 0;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    wave_sync_lds();
 
+    int xq = int(blockIdx.x % kXcd);
+    int exhausted = 0;
     for (;;) {
         unsigned item = 0;
-        if (lane == 0) item = atomicAdd(queue, 1u);
+        if (lane == 0) item = p.qstart[xq] + atomicAdd(&queue[xq], 1u);
         item = __builtin_amdgcn_readfirstlane(item);
-        if (int64_t(item) >= p.n_items) break;
+        if (item >= p.qstart[xq + 1]) {
+            if (++exhausted == kXcd) break;
+            xq = (xq + 1) % kXcd;
+            continue;
+        }
         int task, g;
         if (p.single_task >= 0) {
             task = p.single_task;
@@ -259,73 +362,171 @@ __global__ __launch_bounds__(512) void k_pair_count(
         }
         task = __builtin_amdgcn_readfirstlane(task);
         if (task != w.cur_task) {
-            if (w.cur_task >= 0) flush<LOS, UNIFORM>(w, lane, p, e2tab, counts);
+            if (w.cur_task >= 0) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
             w.cur_task = task;
         }
         const int2 tk = tasks[task];
         const bool autop = tk.x == tk.y;
         const int64_t abase = int64_t(tk.x) * p.ncell, bbase = int64_t(tk.y) * p.ncell;
-        const int64_t c0 = int64_t(g) * p.cells_per_item;
-        const int64_t c1 = min(c0 + p.cells_per_item, p.ncell);
+        const int c0 = g * p.cells_per_item;
+        const int c1 = min(c0 + p.cells_per_item, int(p.ncell));
         const int ns = autop ? p.nhalf : p.nfull;
-        for (int64_t c = c0; c < c1; ++c) {
-            const int64_t ia0 = cs[abase + c], ia1 = cs[abase + c + 1];
+        const int nx = p.n[0], ny = p.n[1], nz = p.n[2];
+        const int32_t* ox = otab;
+        const int32_t* oy = otab + nx;
+        const int32_t* oz = otab + nx + ny;
+        const int box = int(p.box);
+        const int nsub = p.nsub, sub = p.sub;
+        // this lane's sub-cell (lanes >= nsub test nothing)
+        const int slx = lane % sub, sly = (lane / sub) % sub, slz = lane / (sub * sub);
+        for (int c = c0; c < c1; ++c) {
+            const int64_t ia0 = cs[(abase + c) * nsub], ia1 = cs[(abase + c + 1) * nsub];
             if (ia0 == ia1) continue;
-            const int cx = int(c % p.nx);
-            const int64_t t = c / p.nx;
-            const int cy = int(t % p.ny);
-            const int cz = int(t / p.ny);
+            const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
+            const int oix = ox[cx], oiy = oy[cy], oiz = oz[cz];
             for (int64_t ib = ia0; ib < ia1; ib += 64) {
+                // i chunk: one point per lane (i cell frame); lanes past it hold
+                // a sentinel on the opposite side from the j sentinel
                 const int64_t gi = ib + lane;
-                double xi = 1e30, yi = 1e30, zi = 1e30;
-                if (gi < ia1) {
-                    const double4 q = pts[gi];
-                    xi = q.x;
-                    yi = q.y;
-                    zi = q.z;
+                const bool valid = gi < ia1;
+                float xi = 1e18f, yi = 1e18f, zi = 1e18f;
+                if (valid) {
+                    xi = pts[3 * gi];
+                    yi = pts[3 * gi + 1];
+                    zi = pts[3 * gi + 2];
+                    if (LOS == 1) {
+                        w.itab[3 * lane] = int(xi) + oix;
+                        w.itab[3 * lane + 1] = int(yi) + oiy;
+                        w.itab[3 * lane + 2] = int(zi) + oiz;
+                    }
                 }
-                const int64_t nvalid = min(int64_t(64), ia1 - ib);
+                const int n_i = int(min(int64_t(64), ia1 - ib));
+                // bounding box of the chunk's points
+                float blx = valid ? xi : 3e38f, bly = valid ? yi : 3e38f, blz = valid ? zi : 3e38f;
+                float bhx = valid ? xi : -3e38f, bhy = valid ? yi : -3e38f, bhz = valid ? zi : -3e38f;
+                for (int o = 32; o > 0; o >>= 1) {
+                    blx = fminf(blx, __shfl_xor(blx, o));
+                    bly = fminf(bly, __shfl_xor(bly, o));
+                    blz = fminf(blz, __shfl_xor(blz, o));
+                    bhx = fmaxf(bhx, __shfl_xor(bhx, o));
+                    bhy = fmaxf(bhy, __shfl_xor(bhy, o));
+                    bhz = fmaxf(bhz, __shfl_xor(bhz, o));
+                }
+                // j points gathered into blocks of 64 (one per lane) across runs
+                // of kept sub-cells and stencil offsets
+                JBlock jb_pend;
+                jb_pend.idx = 0;
+                jb_pend.ox = jb_pend.oy = jb_pend.oz = 0.0f;
+                jb_pend.self = false;
+                int fill = 0;
+                auto process = [&](int nfill) {
+                    const bool vj = lane < nfill;
+                    float xj = -1e18f, yj = -1e18f, zj = -1e18f;
+                    if (vj) {
+                        xj = pts[3 * jb_pend.idx] + jb_pend.ox;
+                        yj = pts[3 * jb_pend.idx + 1] + jb_pend.oy;
+                        zj = pts[3 * jb_pend.idx + 2] + jb_pend.oz;
+                    }
+                    const int64_t jcmp = (vj && jb_pend.self) ? jb_pend.idx : INT64_MAX;
+                    const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
+                    w.n_cand += nc;
+                    // a uint32 histogram bin holds at most the candidate tests
+                    // since the last flush: flush before that bound could reach 2^32
+                    if (w.since_flush + nc >= 0xFFFFFFFFull) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
+                    w.since_flush += nc;
+                    if (__builtin_amdgcn_ballot_w64(vj && jb_pend.self))
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jcmp, pts, ib, n_i, p,
+                                                                  e2tab);
+                    else
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jcmp, pts, ib, n_i, p,
+                                                                   e2tab);
+                };
                 for (int s = 0; s < ns; ++s) {
                     const int4 o = sten[s];
                     int jx = cx + o.x, jy = cy + o.y, jz = cz + o.z;
-                    double shx = 0.0, shy = 0.0, shz = 0.0;
+                    int shx = 0, shy = 0, shz = 0;
                     if (p.periodic) {
-                        if (jx < 0) { jx += p.nx; shx = -p.boxd; } else if (jx >= p.nx) { jx -= p.nx; shx = p.boxd; }
-                        if (jy < 0) { jy += p.ny; shy = -p.boxd; } else if (jy >= p.ny) { jy -= p.ny; shy = p.boxd; }
-                        if (jz < 0) { jz += p.nz; shz = -p.boxd; } else if (jz >= p.nz) { jz -= p.nz; shz = p.boxd; }
-                    } else if (jx < 0 || jx >= p.nx || jy < 0 || jy >= p.ny || jz < 0 || jz >= p.nz) {
+                        if (jx < 0) { jx += nx; shx = -box; } else if (jx >= nx) { jx -= nx; shx = box; }
+                        if (jy < 0) { jy += ny; shy = -box; } else if (jy >= ny) { jy -= ny; shy = box; }
+                        if (jz < 0) { jz += nz; shz = -box; } else if (jz >= nz) { jz -= nz; shz = box; }
+                    } else if (jx < 0 || jx >= nx || jy < 0 || jy >= ny || jz < 0 || jz >= nz) {
                         continue;
                     }
-                    const int64_t jc = (int64_t(jz) * p.ny + jy) * p.nx + jx;
-                    int64_t jb = cs[bbase + jc];
-                    const int64_t je = cs[bbase + jc + 1];
+                    const int jc = (jz * ny + jy) * nx + jx;
+                    const int64_t sbase = (bbase + jc) * nsub;
+                    // origin of the j cell's image in the i cell frame
+                    const float dox = float(ox[jx] + shx - oix);
+                    const float doy = float(oy[jy] + shy - oiy);
+                    const float doz = float(oz[jz] + shz - oiz);
                     const bool self = autop && s == 0;
-                    if (self) jb = ib + 1;
-                    if (jb >= je) continue;
-                    w.n_cand += uint64_t(nvalid) * uint64_t(je - jb);
-                    // image of point j: x_j + shift, so s = x_j - (x_i - shift)
-                    const double sx = xi - shx, sy = yi - shy, sz = zi - shz;
-                    if (self)
-                        scan_range<LOS, UNIFORM, HAS_EMIN, true>(w, lane, jb, je, sx, sy, sz, gi, pts, p,
-                                                                 e2tab, counts);
-                    else
-                        scan_range<LOS, UNIFORM, HAS_EMIN, false>(w, lane, jb, je, sx, sy, sz, gi, pts, p,
-                                                                  e2tab, counts);
+                    unsigned long long runs;
+                    if (self) {
+                        runs = 0;  // i < j inside the i cell: one range, below
+                    } else {
+                        // sub-cells farther than r_max from the chunk's box hold no
+                        // binned pair; their box is widened by 2 units for the
+                        // rounding of the integer cell boundaries
+                        const float lx = dox + float(slx) * p.wf[0] - 2.0f, hx = lx + p.wf[0] + 4.0f;
+                        const float ly = doy + float(sly) * p.wf[1] - 2.0f, hy = ly + p.wf[1] + 4.0f;
+                        const float lz = doz + float(slz) * p.wf[2] - 2.0f, hz = lz + p.wf[2] + 4.0f;
+                        const float gx = fmaxf(0.0f, fmaxf(lx - bhx, blx - hx));
+                        const float gy = fmaxf(0.0f, fmaxf(ly - bhy, bly - hy));
+                        const float gz = fmaxf(0.0f, fmaxf(lz - bhz, blz - hz));
+                        const float g2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+                        runs = __builtin_amdgcn_ballot_w64((lane < nsub) && (g2 < p.emax2_hi));
+                    }
+                    while (self || runs) {
+                        int64_t jb, je;
+                        if (self) {
+                            jb = ib + 1;
+                            je = ia1;
+                        } else {
+                            // next run of consecutive kept sub-cells = one range of points
+                            const int s0 = __builtin_ctzll(runs);
+                            const unsigned long long rest = ~(runs >> s0);
+                            const int e = rest ? s0 + __builtin_ctzll(rest) : 64;
+                            jb = cs[sbase + s0];
+                            je = cs[sbase + e];
+                            runs = (e >= 64) ? 0ull : (runs & (~0ull << e));
+                        }
+                        jb = uniform64(jb);
+                        je = uniform64(je);
+                        while (jb < je) {
+                            // lanes [fill, fill + take) take points jb, jb + 1, ...
+                            const int take = int(min(je - jb, int64_t(64 - fill)));
+                            if (lane >= fill && lane < fill + take) {
+                                jb_pend.idx = jb + (lane - fill);
+                                jb_pend.ox = dox;
+                                jb_pend.oy = doy;
+                                jb_pend.oz = doz;
+                                jb_pend.self = self;
+                            }
+                            fill += take;
+                            jb += take;
+                            if (fill == 64) {
+                                process(64);
+                                fill = 0;
+                            }
+                        }
+                        if (self) break;
+                    }
                 }
+                if (fill > 0) process(fill);
+                // midpoint entries refer to this chunk's i table: bin them before it changes
+                if (LOS == 1 && w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, e2tab);
             }
         }
     }
-    if (w.cur_task >= 0) flush<LOS, UNIFORM>(w, lane, p, e2tab, counts);
+    if (w.cur_task >= 0) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
     if (stats && lane == 0) {
         atomicAdd(&stats[0], (unsigned long long)w.n_cand);
-        atomicAdd(&stats[1], (unsigned long long)w.n_binned);
         atomicAdd(&stats[2], (unsigned long long)w.n_exact);
         atomicAdd(&stats[3], (unsigned long long)w.n_flush);
     }
 }
 
-typedef void (*PcKernel)(const double4*, const int64_t*, const int2*, const int32_t*, const int4*,
-                         const double*, unsigned long long*, unsigned long long*, unsigned*, PcParams);
+typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_t*, const int4*, const int64_t*,
+                         const int32_t*, unsigned long long*, unsigned long long*, unsigned*, PcParams);
 
 static PcKernel pick_kernel(int los, bool uniform, bool has_emin) {
     static const PcKernel tab[2][2][2] = {
@@ -356,13 +557,19 @@ struct Plan {
     std::vector<int> task_blocks;   // per-task grid (LC_PER_TASK)
     // staged device block layout
     std::vector<unsigned char> blob;
-    size_t off_tasks, off_order, off_sten, off_e2, off_queue;
+    size_t off_tasks, off_order, off_sten, off_e2, off_otab, off_queue;
     int n_queue;
 };
 
-static float f32_up(double v) {  // float >= v
+static float f32_up(double v) {  // smallest float >= v
     float f = float(v);
     if (double(f) < v) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+static float f32_down(double v) {  // largest float <= v
+    float f = float(v);
+    if (double(f) > v) f = std::nextafter(f, -INFINITY);
     return f;
 }
 
@@ -372,20 +579,37 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     const int n_r = b->n_r, n_mu = b->n_mu;
     PcParams& p = pl.p;
     std::memset(&p, 0, sizeof p);
-    p.nx = g.n[0];
-    p.ny = g.n[1];
-    p.nz = g.n[2];
+    for (int a = 0; a < 3; a++) {
+        p.n[a] = g.n[a];
+        p.lo[a] = g.lo[a];
+        p.ext[a] = g.ext[a];
+    }
     p.periodic = g.periodic;
+    p.box = g.box;
     p.ncell = g.ncell;
-    p.boxd = double(g.box);
+    p.sub = g.sub;
+    p.nsub = g.nsub;
+    for (int a = 0; a < 3; a++) p.wf[a] = float(double(g.ext[a]) / (double(g.n[a]) * g.sub));
     std::vector<int4> sten;
     const int64_t rmax = b->r_edges[n_r];
     p.nhalf = build_stencil(g, rmax, sten);
     p.nfull = int(sten.size());
+    // relative coordinates and the cell-origin offsets used in float32 must
+    // stay below 2^24 in magnitude (exact integers)
+    for (int a = 0; a < 3; a++) {
+        int kmax = 0;
+        for (const int4& o : sten) kmax = std::max(kmax, std::abs(a == 0 ? o.x : a == 1 ? o.y : o.z));
+        const int64_t w = (g.ext[a] + g.n[a] - 1) / g.n[a];
+        if ((int64_t(kmax) + 1) * w >= (int64_t(1) << 24))
+            return fail(LC_ERR_RANGE, "cells of %lld units with a stencil of %d cells exceed the float32 "
+                                      "coordinate range; build the mesh with smaller cells",
+                        (long long)w, kmax);
+    }
     int cpi = tune && tune->cells_per_item > 0 ? tune->cells_per_item : 0;
     if (cpi <= 0) {
-        // about 16 items per wave slot over the whole batch, at least one row of cells
-        cpi = std::max(1, g.n[0]);
+        // batched: one row of cells per item (neighbouring items share their j
+        // cells); one launch per task: single cells, to spread a task widest
+        cpi = (mode & LC_PER_TASK) ? 1 : std::max(1, g.n[0]);
     }
     cpi = int(std::min<int64_t>(cpi, g.ncell));
     p.cells_per_item = cpi;
@@ -395,31 +619,43 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.nbins = n_r * n_mu;
     p.hist_stride = (p.nbins + 3) & ~3;
     const bool mid = b->los == LC_LOS_MID;
-    p.wave_bytes = p.hist_stride * 4 + kQ * 16 + (mid ? kQ * 8 : 0);
+    p.wave_bytes = p.hist_stride * 4 + kQ * 16 + (mid ? 64 * 12 : 0);
     const int64_t e0 = b->r_edges[0];
-    p.emin2 = double(e0) * double(e0);
-    p.emax2 = double(rmax) * double(rmax);
+    const int64_t de = int64_t(b->r_edges[1]) - b->r_edges[0];
     bool uniform = true;
-    const int64_t de = b->r_edges[1] - b->r_edges[0];
     for (int k = 0; k <= n_r; k++)
         if (int64_t(b->r_edges[k]) != e0 + int64_t(k) * de) uniform = false;
-    p.e0d = double(e0);
-    p.ded = double(de);
-    p.e0f = float(e0);
+    p.emin2 = e0 * e0;
+    p.emax2 = rmax * rmax;
+    // phase A acceptance: the float32 squared distance is within 3 * 2^-24
+    // (relative) of the exact one, inside the 2^-20 margins used here
+    p.emax2_hi = f32_up(double(p.emax2) * (1.0 + std::ldexp(1.0, -20)));
+    p.emin2_lo = f32_down(double(p.emin2) * (1.0 - std::ldexp(1.0, -20)));
+    p.e0 = e0;
+    p.de = de;
     p.inv_drf = float(1.0 / double(de));
+    p.e0_over_drf = float(double(e0) / double(de));
     p.nmuf = float(n_mu);
-    // Float32 error bounds (relative, in units of 2^-24):
-    //  mu estimate  n_mu |s_z| rsq(d2): conversions 1 + 0.5, rsq 2, two products 2  -> 5.5
-    //  (midpoint adds p, q conversions, a second rsq and a product: -> 10)
-    //  r estimate   d2 * rsq(d2): 0.5 + 2 + 1 = 3.5 of r; then (r - e0) * (1/de): 3 more
-    // The margins below are 4-6x these bounds; anything closer to an edge is
-    // decided with integers.
+    // Float32 error bounds in units of u = 2^-24 (relative error per rounding;
+    // v_rsq_f32 is within 1 ulp = 2u):
+    //   d2 (float32 sum of exact squares): 3u
+    //   mu estimate |s_z| rsq(d2) n_mu: 1.5u (from d2) + 2u + two products 2u
+    //     -> 5.5u n_mu absolute; midpoint: p and q conversions, rsq(q), one
+    //     more product -> 10u n_mu
+    //   r estimate d2 rsq(d2): 1.5u + 2u + 1u = 4.5u of r; t = r/de - e0/de by
+    //     one fma with rounded 1/de and e0/de -> u (5.5 r_max + e0)/de + u n_r
+    // The margins are 4x these bounds; pairs closer to an edge take the
+    // integer rule.
     const double u = std::ldexp(1.0, -24);
-    double em = (mid ? 10.0 : 5.5) * u * n_mu;
+    const double em = (mid ? 10.0 : 5.5) * u * n_mu;
     p.eps_m = f32_up(std::max(4.0 * em, std::ldexp(1.0, -22)));
     p.nmu_m1_eps = f32_up(double(n_mu - 1) + double(p.eps_m));
-    double er = 3.5 * u * double(rmax) / double(de) + 3.0 * u * double(n_r);
-    p.eps_r = f32_up(std::max(4.0 * er, std::ldexp(1.0, -22)));
+    const double er = u * ((5.5 * double(rmax) + double(e0)) / double(de) + double(n_r));
+    // plus the distance of an accepted pair outside [e_0, e_n) from the edge:
+    // phase A accepts d2 < e_n^2 (1 + 2^-20) and d2 >= e_0^2 (1 - 2^-20), i.e.
+    // |r - edge| < 2^-20 edge, which is at most 2^-20 r_max / de in units of t
+    const double margin_t = std::ldexp(double(rmax) / double(de), -20);
+    p.eps_r = f32_up(std::max(4.0 * er + 2.0 * margin_t, std::ldexp(1.0, -22)));
     p.force_exact = (mode & LC_FORCE_EXACT) ? 1 : 0;
     const bool has_emin = e0 > 0;
     pl.kern = pick_kernel(mid ? 1 : 0, uniform, has_emin);
@@ -458,21 +694,37 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost[x] > cost[y]; });
     const int64_t n_items = int64_t(n_tasks) * p.items_per_task;
     if (n_items >= (int64_t(1) << 31))
-        return fail(LC_ERR_OVERFLOW, "%lld work items exceed the 32-bit queue", (long long)n_items);
+        return fail(LC_ERR_OVERFLOW, "%lld work items exceed the 31-bit queue", (long long)n_items);
     const bool per_task = (mode & LC_PER_TASK) != 0;
-    p.n_items = per_task ? p.items_per_task : n_items;
     p.single_task = -1;
-    pl.n_queue = per_task ? n_tasks : 1;
     if (per_task) {
+        // one queue holds the task's items; the other queues start empty
+        p.qstart[0] = 0;
+        for (int x = 1; x <= kXcd; x++) p.qstart[x] = uint32_t(p.items_per_task);
+        pl.n_queue = n_tasks * kXcd;
         pl.task_blocks.resize(n_tasks);
         for (int t = 0; t < n_tasks; t++) {
             int64_t need = (p.items_per_task + wpb - 1) / wpb;
             pl.task_blocks[t] = int(std::max<int64_t>(1, std::min<int64_t>(need, pl.blocks)));
         }
+    } else {
+        // split the ordered tasks into kXcd contiguous ranges of equal cost;
+        // waves of XCD x start on range x and move on when it is empty
+        double total = 0;
+        for (int t = 0; t < n_tasks; t++) total += cost[t];
+        p.qstart[0] = 0;
+        double acc = 0;
+        int x = 1;
+        for (int s = 0; s < n_tasks && x < kXcd; s++) {
+            acc += cost[order[s]];
+            while (x < kXcd && acc >= total * x / kXcd) p.qstart[x++] = uint32_t(int64_t(s + 1) * p.items_per_task);
+        }
+        for (; x <= kXcd; x++) p.qstart[x] = uint32_t(n_items);
+        pl.n_queue = kXcd;
     }
     // staged block: tasks, order, stencil, squared edges, zeroed queue counters
-    std::vector<double> e2(n_r + 1);
-    for (int k = 0; k <= n_r; k++) e2[k] = double(b->r_edges[k]) * double(b->r_edges[k]);
+    std::vector<int64_t> e2(n_r + 1);
+    for (int k = 0; k <= n_r; k++) e2[k] = int64_t(b->r_edges[k]) * int64_t(b->r_edges[k]);
     std::vector<unsigned> qz(pl.n_queue, 0u);
     auto put = [&](const void* src, size_t bytes) {
         size_t off = (pl.blob.size() + 255) & ~size_t(255);
@@ -483,7 +735,12 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     pl.off_tasks = put(tasks, sizeof(lc_task) * n_tasks);
     pl.off_order = put(order.data(), sizeof(int32_t) * n_tasks);
     pl.off_sten = put(sten.data(), sizeof(int4) * sten.size());
-    pl.off_e2 = put(e2.data(), sizeof(double) * e2.size());
+    pl.off_e2 = put(e2.data(), sizeof(int64_t) * e2.size());
+    // integer origin of every cell index along x, y and z
+    std::vector<int32_t> ot;
+    for (int a = 0; a < 3; a++)
+        for (int c = 0; c < g.n[a]; c++) ot.push_back(int32_t(cell_origin(c, g.lo[a], g.ext[a], g.n[a])));
+    pl.off_otab = put(ot.data(), sizeof(int32_t) * ot.size());
     pl.off_queue = put(qz.data(), sizeof(unsigned) * qz.size());
     return LC_OK;
 }
@@ -493,7 +750,8 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
     const int2* d_tasks = reinterpret_cast<const int2*>(dev + pl.off_tasks);
     const int32_t* d_order = reinterpret_cast<const int32_t*>(dev + pl.off_order);
     const int4* d_sten = reinterpret_cast<const int4*>(dev + pl.off_sten);
-    const double* d_e2 = reinterpret_cast<const double*>(dev + pl.off_e2);
+    const int64_t* d_e2 = reinterpret_cast<const int64_t*>(dev + pl.off_e2);
+    const int32_t* d_ot = reinterpret_cast<const int32_t*>(dev + pl.off_otab);
     unsigned* d_q = reinterpret_cast<unsigned*>(dev + pl.off_queue);
     auto* c = reinterpret_cast<unsigned long long*>(counts);
     auto* st = reinterpret_cast<unsigned long long*>(stats);
@@ -502,11 +760,11 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
         for (int t = 0; t < pl.n_tasks; t++) {
             p.single_task = t;
             hipLaunchKernelGGL(pl.kern, dim3(pl.task_blocks[t]), dim3(pl.threads), pl.lds, s, cells->pts,
-                               cells->cs, d_tasks, d_order, d_sten, d_e2, c, st, d_q + t, p);
+                               cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q + kXcd * t, p);
         }
     } else {
         hipLaunchKernelGGL(pl.kern, dim3(pl.blocks), dim3(pl.threads), pl.lds, s, cells->pts, cells->cs,
-                           d_tasks, d_order, d_sten, d_e2, c, st, d_q, pl.p);
+                           d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q, pl.p);
     }
 }
 

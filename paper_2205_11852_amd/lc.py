@@ -57,9 +57,15 @@ class lc_tuning(ctypes.Structure):
                 ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class lc_mesh_opts(ctypes.Structure):
+    _fields_ = [("cell_units", ctypes.c_int32), ("sub", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
 class lc_cells_info(ctypes.Structure):
     _fields_ = [("n_cat", ctypes.c_int32), ("grid", ctypes.c_int32 * 3),
-                ("cell_side", ctypes.c_double * 3), ("n_total", ctypes.c_int64),
+                ("cell_side", ctypes.c_double * 3), ("sub", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("n_total", ctypes.c_int64),
                 ("bytes", ctypes.c_int64)]
 
 
@@ -89,8 +95,8 @@ def lib():
     L.lc_last_error.restype = ctypes.c_char_p
     L.lc_last_error.argtypes = []
     L.lc_build_cells.restype = st
-    L.lc_build_cells.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning), i32, vp,
-                                 ctypes.POINTER(vp)]
+    L.lc_build_cells.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning),
+                                 ctypes.POINTER(lc_mesh_opts), vp, ctypes.POINTER(vp)]
     L.lc_free_cells.restype = None
     L.lc_free_cells.argtypes = [vp]
     L.lc_cells_get_info.restype = st
@@ -185,7 +191,7 @@ class Cells:
         inf = lc_cells_info()
         _check(lib().lc_cells_get_info(self.handle, ctypes.byref(inf)))
         return {"n_cat": inf.n_cat, "grid": list(inf.grid), "cell_side": list(inf.cell_side),
-                "n_total": inf.n_total, "bytes": inf.bytes}
+                "sub": inf.sub, "n_total": inf.n_total, "bytes": inf.bytes}
 
     def close(self):
         if self.handle:
@@ -199,16 +205,19 @@ class Cells:
             pass
 
 
-def lc_build_cells(xyz, cat_offsets, binning: Binning, cell_units: int = 0, stream=None) -> Cells:
-    """xyz: int32 device tensor [3, n_total]; cat_offsets: int64 [n_cat+1]."""
+def lc_build_cells(xyz, cat_offsets, binning: Binning, cell_units: int = 0, sub: int = 0,
+                   stream=None) -> Cells:
+    """xyz: int32 device tensor [3, n_total]; cat_offsets: int64 [n_cat+1];
+    cell_units / sub: mesh options (0 = library defaults)."""
     off = np.ascontiguousarray(np.asarray(cat_offsets, dtype=np.int64))
     n_total = int(off[-1]) if len(off) else 0
     if xyz is not None and not isinstance(xyz, int):
         if tuple(xyz.shape) != (3, n_total) or str(xyz.dtype) != "torch.int32" or not xyz.is_contiguous():
             raise ValueError("xyz must be a contiguous int32 tensor of shape (3, %d)" % n_total)
     out = ctypes.c_void_p()
+    opts = lc_mesh_opts(int(cell_units), int(sub))
     _check(lib().lc_build_cells(_dptr(xyz), n_total, off.ctypes.data, len(off) - 1,
-                                ctypes.byref(binning.c), int(cell_units), _stream(stream),
+                                ctypes.byref(binning.c), ctypes.byref(opts), _stream(stream),
                                 ctypes.byref(out)))
     return Cells(out.value)
 

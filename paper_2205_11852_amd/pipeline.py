@@ -67,10 +67,10 @@ class Pipeline:
         self._nb = nb
 
     # -- steps ---------------------------------------------------------------
-    def build_cells(self, cell_units: int = 0):
+    def build_cells(self, cell_units: int = 0, sub: int = 0):
         if self.cells is not None:
             self.cells.close()
-        self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units)
+        self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units, sub)
         return self.cells
 
     def count(self, mode: int = lc.LC_PERSISTENT, tune: Optional[dict] = None, zero: bool = True):
@@ -118,9 +118,9 @@ class Pipeline:
                                 self.M if M is None else M, precision, self.A, self.B, self.C, report)
 
     def run(self, mode: int = lc.LC_PERSISTENT, precision: int = lc.LC_FP32_MFMA, report: bool = True,
-            cell_units: int = 0, tune: Optional[dict] = None) -> dict:
+            cell_units: int = 0, sub: int = 0, tune: Optional[dict] = None) -> dict:
         """The whole path on device-resident catalogues; returns the check report."""
-        self.build_cells(cell_units)
+        self.build_cells(cell_units, sub)
         self.count(mode, tune)
         self.xi_multipoles()
         return self.covariance(precision, report)
@@ -131,5 +131,5 @@ class Pipeline:
 
     def stats_host(self) -> Dict[str, int]:
         s = self.stats.cpu().numpy().view(np.uint64)
-        return {"candidates": int(s[0]), "binned": int(s[1]), "exact_fallback": int(s[2]),
-                "flushes": int(s[3])}
+        return {"candidates": int(s[0]), "binned": int(self.counts_host().sum(dtype=np.uint64)),
+                "exact_fallback": int(s[2]), "flushes": int(s[3])}

@@ -51,7 +51,7 @@ def _binning(**kw):
 def _build_status(L, b, n_total=4, offsets=(0, 4), out=True, xyz=0x1000):
     off = np.array(offsets, dtype=np.int64)
     h = ctypes.c_void_p()
-    return L.lc_build_cells(xyz, n_total, off.ctypes.data, len(off) - 1, ctypes.byref(b.c), 0, None,
+    return L.lc_build_cells(xyz, n_total, off.ctypes.data, len(off) - 1, ctypes.byref(b.c), None, None,
                             ctypes.byref(h) if out else None)
 
 
@@ -71,6 +71,16 @@ def _build_status(L, b, n_total=4, offsets=(0, 4), out=True, xyz=0x1000):
 def test_build_cells_rejects_bad_binning(L, kw, code):
     assert _build_status(L, _binning(**kw)) == code
     assert lc.last_error()
+
+
+def test_build_cells_rejects_bad_options(L):
+    b = _binning()
+    off = np.array([0, 4], dtype=np.int64)
+    h = ctypes.c_void_p()
+    for opts in (lc.lc_mesh_opts(0, 3), lc.lc_mesh_opts(-5, 0)):
+        st = L.lc_build_cells(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), ctypes.byref(opts), None,
+                              ctypes.byref(h))
+        assert st == lc.LC_ERR_INVALID
 
 
 def test_build_cells_rejects_bad_layout(L):

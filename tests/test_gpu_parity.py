@@ -75,8 +75,10 @@ def test_c1_modes_identical(c1, lcmod, torch, mode_name):
         torch.cuda.synchronize()
         assert np.array_equal(pl.counts_host(), c1["ref"]), (mode_name, r)
     if mode_name == "force_exact":
+        # every queued pair took the integer rule: the binned ones plus the few
+        # that phase A's float margin let through and the rule then dropped
         st = pl.stats_host()
-        assert st["exact_fallback"] == st["binned"]
+        assert st["binned"] <= st["exact_fallback"] <= st["binned"] * (1 + 1e-4)
 
 
 def test_c1_per_mock_baseline_identical(c1, torch):
@@ -96,14 +98,15 @@ def test_c1_tunings_identical(c1, torch, tune):
     assert np.array_equal(pl.counts_host(), c1["ref"])
 
 
-@pytest.mark.parametrize("cell_mpc", [25.0, 33.0, 50.0, 100.0, 160.0])
-def test_c1_cell_sizes_identical(c1, torch, cell_mpc):
+@pytest.mark.parametrize("cell_mpc,sub", [(25.0, 1), (33.0, 2), (50.0, 4), (100.0, 1), (100.0, 2),
+                                          (100.0, 4), (160.0, 4), (240.0, 4)])
+def test_c1_cell_sizes_identical(c1, torch, cell_mpc, sub):
     pl = c1["pl"]
-    _say("[c1] cell", cell_mpc)
-    pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC))
+    _say("[c1] cell", cell_mpc, "sub", sub)
+    pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC), sub)
     pl.count()
     torch.cuda.synchronize()
-    assert np.array_equal(pl.counts_host(), c1["ref"]), cell_mpc
+    assert np.array_equal(pl.counts_host(), c1["ref"]), (cell_mpc, sub)
     pl.build_cells()
 
 
@@ -264,9 +267,9 @@ def test_wedge_midpoint_bit_exact(torch, oracle_mod, lcmod):
                              n_subsets=2, subset_size=6000)
     cats = mockgen.make_catalogues(wl)
     pl = Pipeline(cats)
-    for cell_mpc in (0, 60.0, 200.0):
-        _say("[wedge] cell", cell_mpc)
-        pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC))
+    for cell_mpc, sub in ((0, 0), (60.0, 1), (60.0, 4), (200.0, 2)):
+        _say("[wedge] cell", cell_mpc, "sub", sub)
+        pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC), sub)
         pl.count()
         torch.cuda.synchronize()
         gpu = pl.counts_host()
@@ -292,7 +295,7 @@ def test_ragged_catalogues(torch, oracle_mod, lcmod):
     for edges in ([0, 100, 900, 2000, 3000, 6000], [40, 50, 64, 1000, 1001, 4321, 9000]):
         for n_mu in (1, 3, 10):
             bn = lcmod.Binning(edges, n_mu, True, L, lcmod.LC_LOS_Z)
-            cells = lcmod.lc_build_cells(xyz, off, bn)
+            cells = lcmod.lc_build_cells(xyz, off, bn, sub=(1, 2, 4)[n_mu % 3])
             counts = torch.zeros((len(tasks), bn.n_r, n_mu), dtype=torch.int64, device="cuda")
             lcmod.lc_pair_count_batch(cells, tasks, bn, counts)
             got = counts.cpu().numpy().view(np.uint64)
