@@ -36,6 +36,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """sha256[:16] of the pair-count kernel's sources (paircount.hip, lc_internal.hpp)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("paircount.hip", "lc_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2205_11852_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(config: str, n_mock: int, wl_mocks: int):
+    """HBM bytes per launch of the pair-count kernel from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary (copy-calibrated), or None when
+    the summary is missing, was taken on another workload, or the kernel
+    source has changed since the counters were read."""
+    path = os.path.join(ROOT, "profiles", "k_pair_count_%s_traffic.md" % config)
+    if n_mock != wl_mocks or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.split(":")[0] in ("traffic_bytes_per_launch", "kernel_source"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
+        return None
+    return int(kv["traffic_bytes_per_launch"])
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,7 +158,8 @@ def main():
         "exact_fallback_fraction": st["exact_fallback"] / max(binned, 1),
         "check_report": rep,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / PEAK_OPS, "traffic": None},
+                     "unit": "TOP/s", "frac": achieved / PEAK_OPS,
+                     "traffic": measured_traffic(args.config, n_mock, wl.n_mock)},
     }
 
     if not args.no_per_mock:

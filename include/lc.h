@@ -83,7 +83,7 @@ typedef struct {
                                  96 points per cell of a mean catalogue, kept within
                                  [r_max / 3, r_max]); rounded so cells tile the box */
     int32_t sub;              /* sub-cells per axis inside a coarse cell: 1, 2 or 4
-                                 (default 4); pair counting skips the sub-cells that
+                                 (default 2); pair counting skips the sub-cells that
                                  lie beyond r_max of each group of 64 points */
     int32_t reserved[2];
 } lc_mesh_opts;

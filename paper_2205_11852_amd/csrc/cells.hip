@@ -302,7 +302,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     *out = nullptr;
     LC_TRY(check_binning(b));
     const int32_t cell_units = opts ? opts->cell_units : 0;
-    int32_t sub = opts && opts->sub ? opts->sub : 4;
+    int32_t sub = opts && opts->sub ? opts->sub : 2;
     if (sub != 1 && sub != 2 && sub != 4) return fail(LC_ERR_INVALID, "sub = %d, must be 1, 2 or 4", sub);
     if (n_cat < 1) return fail(LC_ERR_INVALID, "n_cat = %d, must be >= 1", n_cat);
     if (!cat_offsets) return fail(LC_ERR_INVALID, "cat_offsets is NULL");
