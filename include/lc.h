@@ -135,9 +135,11 @@ typedef struct { int32_t cat_a, cat_b; } lc_task;
 /* Tuning knobs; NULL or 0 fields = library defaults. */
 typedef struct {
     int32_t cells_per_item;   /* cells of one catalogue per work item */
-    int32_t waves_per_block;  /* 1, 2, 4, 8 */
+    int32_t waves_per_block;  /* 1, 2, 4, 8 (default 4): waves sharing a work item and a histogram */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
-    int32_t reserved;
+    int32_t chunk;            /* i points tested together against each gathered j set:
+                                 a multiple of 4 in [4, 256] ([4, 64] for LC_LOS_MID);
+                                 default the maximum */
 } lc_tuning;
 
 /*

@@ -26,6 +26,8 @@
 // drops pairs that phase A's margin let through.  Bins go to a wave-private
 // uint32 LDS histogram flushed with uint64 global atomics when the wave
 // moves to another task.
+#include <climits>
+#include <cstddef>
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -52,18 +54,29 @@ struct PcParams {
     int32_t pad1;
     int32_t nhalf, nfull;
     int32_t cells_per_item, items_per_task;
+    int32_t chunk, pad3;        // i points per chunk (multiple of 4, <= 64)
     int32_t n_r, n_mu, nbins;
-    int32_t hist_stride;    // uint32 words per wave histogram
-    int32_t wave_bytes;     // LDS bytes per wave
-    int32_t force_exact;
+    int32_t hist_stride;    // uint32 words per wave histogram (bins + a discard slot)
+    int32_t queue_byte0;    // LDS byte offset of wave 0's queue
+    int32_t pad2;
     float emax2_hi, emin2_lo;   // phase A acceptance (float32, with margin)
-    int64_t emin2, emax2;       // exact squared edges
-    int64_t e0, de;             // uniform edges: e_k = e0 + k de
-    float inv_drf, e0_over_drf, nmuf, nmu_m1_eps, eps_r, eps_m;
+    float inv_drf, e0_over_drf, nmuf, eps_r, eps_m;
+    uint32_t wave_limit;        // candidate tests a wave may register between flushes
     uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
 
 typedef unsigned __int128 u128;
+
+// Constants of the integer rule.  Kept in device memory and read only on that
+// (rare) path, so that they hold no registers in the loops.
+struct ExactTab {
+    int64_t emin2, emax2;   // exact squared outer edges
+    int64_t e0, de;         // uniform edges: e_k = e0 + k de
+    int32_t n_r, n_mu;
+    int32_t discard;        // histogram slot of dropped pairs (= n_r n_mu)
+    int32_t pad;
+    int64_t e2[1];          // [n_r + 1] squared edges (flexible tail)
+};
 
 // A value every lane holds equally, made visible as such to the compiler so
 // that loads indexed by it become scalar loads.
@@ -83,50 +96,100 @@ __device__ __forceinline__ int exact_mu(u128 den, u128 num, int m_est, int n_mu)
     return m;
 }
 
-// Integer rule (the binning of Sect. 4.3 with exact comparisons): the bin of
-// separation s (midpoint: P = s.l, Q = l.l), or -1 outside [e_0, e_n).
-template <int LOS, bool UNIFORM>
-__device__ __forceinline__ int exact_bin(int64_t sx, int64_t sy, int64_t sz, int64_t P, uint64_t Q,
-                                         int k_est, int m_est, const PcParams& p,
-                                         const int64_t* __restrict__ e2tab) {
-    const uint64_t D2 = sq64(sx) + sq64(sy) + sq64(sz);
-    if (D2 >= uint64_t(p.emax2) || D2 < uint64_t(p.emin2)) return -1;
+// a * b <= c * d, exactly, for float64 operands whose products do not
+// underflow: each product is p + (fma(a, b, -p)) exactly, and rounding is
+// monotonic, so the pairs (p, low part) order like the exact products.
+__device__ __forceinline__ bool prod_le(double a, double b, double c, double d) {
+    const double p = a * b, q = c * d;
+    if (p != q) return p < q;
+    return fma(a, b, -p) <= fma(c, d, -q);
+}
+
+// Integer rule for the plane-parallel line of sight, in float64: the
+// separation components are integers below 2^25, so their squares and d^2
+// (below 2^52), the squared edges and m^2, n_mu^2 (below 2^20) are exact;
+// the mu test m^2 d^2 <= n_mu^2 s_z^2 is decided exactly by prod_le.
+template <bool UNIFORM>
+__device__ __forceinline__ int exact_bin_z(double x, double y, double z, int k_est, int m_est,
+                                           const ExactTab* __restrict__ xt) {
+    const double D2 = fma(x, x, fma(y, y, z * z));
+    if (D2 >= double(xt->emax2) || D2 < double(xt->emin2)) return xt->discard;
+    const int n_r = xt->n_r, n_mu = xt->n_mu;
     int k;
     if (UNIFORM) {
-        k = min(max(k_est, 0), p.n_r - 1);
-        while (k > 0 && D2 < sq64(p.e0 + int64_t(k) * p.de)) --k;
-        while (k < p.n_r - 1 && D2 >= sq64(p.e0 + int64_t(k + 1) * p.de)) ++k;
+        const double e0 = double(xt->e0), de = double(xt->de);
+        k = min(max(k_est, 0), n_r - 1);
+        while (k > 0 && D2 < (e0 + k * de) * (e0 + k * de)) --k;
+        while (k < n_r - 1 && D2 >= (e0 + (k + 1) * de) * (e0 + (k + 1) * de)) ++k;
     } else {
-        int lo = 0, hi = p.n_r;  // e2[lo] <= D2 < e2[hi]
+        int lo = 0, hi = n_r;  // e2[lo] <= D2 < e2[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (uint64_t(e2tab[mid]) <= D2) lo = mid;
+            if (double(xt->e2[mid]) <= D2) lo = mid;
             else hi = mid;
         }
         k = lo;
     }
-    const uint64_t nm2 = uint64_t(p.n_mu) * uint64_t(p.n_mu);
+    int m = 0;
+    if (D2 > 0.0) {
+        const double nm2 = double(n_mu) * double(n_mu), z2 = z * z;
+        m = min(max(m_est, 0), n_mu - 1);
+        while (m > 0 && !prod_le(double(m) * double(m), D2, nm2, z2)) --m;
+        while (m < n_mu - 1 && prod_le(double(m + 1) * double(m + 1), D2, nm2, z2)) ++m;
+    }
+    return k * n_mu + m;
+}
+
+// Integer rule (the binning of Sect. 4.3 with exact comparisons): the bin of
+// separation s (midpoint: P = s.l, Q = l.l), or the discard slot outside
+// [e_0, e_n).
+template <int LOS, bool UNIFORM>
+__device__ __forceinline__ int exact_bin(int64_t sx, int64_t sy, int64_t sz, int64_t P, uint64_t Q,
+                                         int k_est, int m_est, const ExactTab* __restrict__ xt) {
+    const uint64_t D2 = sq64(sx) + sq64(sy) + sq64(sz);
+    if (D2 >= uint64_t(xt->emax2) || D2 < uint64_t(xt->emin2)) return xt->discard;
+    const int n_r = xt->n_r, n_mu = xt->n_mu;
+    int k;
+    if (UNIFORM) {
+        const int64_t e0 = xt->e0, de = xt->de;
+        k = min(max(k_est, 0), n_r - 1);
+        while (k > 0 && D2 < sq64(e0 + int64_t(k) * de)) --k;
+        while (k < n_r - 1 && D2 >= sq64(e0 + int64_t(k + 1) * de)) ++k;
+    } else {
+        int lo = 0, hi = n_r;  // e2[lo] <= D2 < e2[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (uint64_t(xt->e2[mid]) <= D2) lo = mid;
+            else hi = mid;
+        }
+        k = lo;
+    }
+    const uint64_t nm2 = uint64_t(n_mu) * uint64_t(n_mu);
     int m;
     if (LOS == 0) {
         const uint64_t AZ = uint64_t(sz < 0 ? -sz : sz);
-        m = (D2 == 0) ? 0 : exact_mu(u128(D2), u128(nm2) * AZ * AZ, m_est, p.n_mu);
+        m = (D2 == 0) ? 0 : exact_mu(u128(D2), u128(nm2) * AZ * AZ, m_est, n_mu);
     } else {
         const uint64_t AP = uint64_t(P < 0 ? -P : P);
-        m = (D2 == 0 || Q == 0) ? 0 : exact_mu(u128(D2) * Q, u128(nm2) * AP * AP, m_est, p.n_mu);
+        m = (D2 == 0 || Q == 0) ? 0 : exact_mu(u128(D2) * Q, u128(nm2) * AP * AP, m_est, n_mu);
     }
-    return k * p.n_mu + m;
+    return k * n_mu + m;
 }
 
 struct WaveState {
-    unsigned* hist;
-    float4* qa;           // linear queue of (sx, sy, sz, d2 | i-lane), entries [0, qtail)
-    int* itab;            // midpoint: absolute coordinates of the current i points
+    unsigned* hist;       // the block's histogram (shared by its waves)
+    float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
+    uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
+    int* itab;            // midpoint: absolute coordinates of the chunk's i points (block)
     uint32_t qtail;       // wave-uniform
-    uint64_t since_flush; // candidate tests since the last flush (bounds every bin)
+    uint32_t since_flush; // candidate tests this wave registered since its last flush
     uint64_t n_cand;
-    uint32_t n_exact, n_flush;
-    int cur_task;
+    uint32_t n_exact;     // per lane: pairs binned by the integer rule
+    uint32_t n_flush;
 };
+
+extern __shared__ __align__(16) unsigned char smem[];
+__device__ __forceinline__ unsigned char* smem_base() { return smem; }
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -134,16 +197,19 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Bin of one queued pair, or -1 (dropped).  The float estimates are kept only
-// when farther than eps from every edge; the clamps to >= 1 make d2 = 0 and
-// q = 0 produce estimates that fail that test, so every value stays finite.
+// Histogram slot of one queued pair (the discard slot when it is dropped).
+// The float estimates are kept only when farther than eps from every edge;
+// the clamps to >= 1 make d2 = 0 and q = 0 produce estimates that fail that
+// test, so every value stays finite.  (eps_r >= 1 sends every pair to the
+// integer rule.)
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__ itab, const PcParams& p,
-                                         const int64_t* __restrict__ e2tab, bool& used_exact) {
+                                         const ExactTab* __restrict__ xt, uint32_t& n_exact) {
     float d2f, u;
     double P = 0.0, Q = 0.0;
     if (LOS == 0) {
-        d2f = __builtin_amdgcn_fmed3f(e.w, 1.0f, 3.0e38f);
+        // d2 = 0 gives rsq = inf and NaN estimates, which fail the edge test
+        d2f = e.w;
         u = fabsf(e.z) * __builtin_amdgcn_rsqf(d2f) * p.nmuf;
     } else {
         // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
@@ -158,9 +224,11 @@ __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__
         u = fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)) *
             p.nmuf;
     }
-    int m = int(u);
+    // |mu| n_mu <= n_mu exactly; an estimate at or above n_mu - eps_m (mu near
+    // 1) fails the test below and takes the integer rule, so m < n_mu here
+    const int m = int(u);
     const float fm = __builtin_amdgcn_fractf(u);
-    bool ok = (u >= p.nmu_m1_eps) | ((fm > p.eps_m) & (fm < 1.0f - p.eps_m));
+    bool ok = (fm > p.eps_m) & (fm < 1.0f - p.eps_m);
     int k = 0;
     if (UNIFORM) {
         // eps_r also covers phase A's acceptance margin, so a pair outside
@@ -173,13 +241,14 @@ __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__
     } else {
         ok = false;  // non-uniform edges: every pair takes the integer rule
     }
-    ok = ok & (p.force_exact == 0);
-    m = min(m, p.n_mu - 1);
-    used_exact = !ok;
-    if (!ok)
-        return exact_bin<LOS, UNIFORM>(int64_t(e.x), int64_t(e.y), int64_t(e.z), int64_t(P), uint64_t(Q), k,
-                                       m, p, e2tab);
-    return k * p.n_mu + m;
+    if (!ok) {
+        n_exact++;
+        if (LOS == 0) return exact_bin_z<UNIFORM>(double(e.x), double(e.y), double(e.z), k, m, xt);
+        return exact_bin<LOS, UNIFORM>(int64_t(int(e.x)), int64_t(int(e.y)), int64_t(int(e.z)), int64_t(P),
+                                       uint64_t(Q), k, m, xt);
+    }
+    // 24-bit multiply: k < n_r and n_mu are far below 2^24
+    return int(__umul24(uint32_t(k), uint32_t(p.n_mu))) + m;
 }
 
 // Bin the last n (<= 64) of the qt queued pairs, one per lane (the queue is
@@ -187,36 +256,49 @@ __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__
 // Returns the new queue length.
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
-                                          const int64_t* __restrict__ e2tab) {
+                                          const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = qt - n;
-    bool ex = false;
     if (uint32_t(lane) < n) {
         const float4 e = w.qa[first + lane];
-        const int bin = bin_entry<LOS, UNIFORM, HAS_E0>(e, w.itab, p, e2tab, ex);
-        if (bin >= 0) __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        const int bin = bin_entry<LOS, UNIFORM, HAS_E0>(e, w.itab, p, xt, w.n_exact);
+        __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
-    w.n_exact += uint32_t(__popcll(__builtin_amdgcn_ballot_w64(ex)));
     wave_sync_lds();
     return __builtin_amdgcn_readfirstlane(first);
 }
 
+// Every bin value is at most the sum over the block's waves of the candidate
+// tests each registered since its last flush; each wave keeps its own share
+// below 2^32 / waves, so no uint32 bin can wrap.  A wave whose share would
+// pass that bound bins its queue and then moves the whole histogram out with
+// atomic exchanges: counts other waves add meanwhile stay in the bins, and
+// their shares still cover them.
 template <int LOS, bool UNIFORM, bool HAS_E0>
-__device__ __forceinline__ void flush(WaveState& w, int lane, const PcParams& p,
-                                      const int64_t* __restrict__ e2tab,
-                                      unsigned long long* __restrict__ counts) {
-    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, e2tab);
-    unsigned long long* dst = counts + int64_t(w.cur_task) * p.nbins;
+__device__ __forceinline__ void wave_flush(WaveState& w, int lane, const PcParams& p,
+                                           const ExactTab* __restrict__ xt,
+                                           unsigned long long* __restrict__ dst) {
+    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, xt);
     for (int b = lane; b < p.nbins; b += 64) {
-        const unsigned v = w.hist[b];
-        if (v) {
-            __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            w.hist[b] = 0;
-        }
+        const unsigned v = __hip_atomic_exchange(&w.hist[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (v) __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    wave_sync_lds();
     w.since_flush = 0;
     w.n_flush++;
+}
+
+// End of a task: every wave has binned its queue; the block adds the
+// histogram into the task's counts and clears it.  Called by all threads.
+__device__ __forceinline__ void block_flush(unsigned* hist, int nbins, unsigned long long* __restrict__ dst) {
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+        const unsigned v = hist[b];
+        if (v) {
+            __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            hist[b] = 0;
+        }
+    }
+    __syncthreads();
 }
 
 struct Cand {
@@ -236,7 +318,7 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
     c.dz = zj - zi;
     c.d2 = fmaf(c.dx, c.dx, fmaf(c.dy, c.dy, c.dz * c.dz));
     c.acc = c.d2 < p.emax2_hi;
-    if (HAS_EMIN) c.acc = c.acc & (c.d2 >= p.emin2_lo);
+    if (HAS_EMIN) c.acc = c.acc && (c.d2 >= p.emin2_lo);
     return c;
 }
 
@@ -245,16 +327,20 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
 // (plane-parallel) or the i index within the chunk (midpoint).
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
-                                         uint32_t qt, const PcParams& p, const int64_t* __restrict__ e2tab) {
+                                         uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
     qt = __builtin_amdgcn_readfirstlane(qt);
     if (bal) {
         if (c.acc) {
+            // slot qt + (accepted lanes below this one), addressed from a
+            // wave-uniform byte base
             const uint32_t rank =
                 __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-            w.qa[qt + rank] = make_float4(c.dx, c.dy, c.dz, LOS == 0 ? c.d2 : w4);
+            const uint32_t base = w.qbyte + qt * 16u;
+            *reinterpret_cast<float4*>(smem_base() + base + rank * 16u) =
+                make_float4(c.dx, c.dy, c.dz, LOS == 0 ? c.d2 : w4);
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
-        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0>(w, lane, 64, qt, p, e2tab);
+        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0>(w, lane, 64, qt, p, xt);
     }
     return qt;
 }
@@ -269,34 +355,37 @@ struct JBlock {
 
 // Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
 // scalar loads) against the j block held one point per lane.  TAIL: some of
-// the four lie past the chunk (in the padded point array) and are replaced by
-// a far sentinel.
+// the four lie past the chunk (still inside the padded point array); their
+// tests are computed and their ballots cleared.
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL>
 __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
-                                                int64_t jcmp, const float* __restrict__ q, int64_t ib, int k,
+                                                int jrel, const float* __restrict__ q, int64_t ib, int k,
                                                 int n_i, uint32_t qt, const PcParams& p,
-                                                const int64_t* __restrict__ e2tab) {
+                                                const ExactTab* __restrict__ xt) {
     float a[12];
 #pragma unroll
     for (int t = 0; t < 12; t++) a[t] = q[t];
-    if (TAIL) {
-#pragma unroll
-        for (int u = 1; u < 4; u++)
-            if (k + u >= n_i) a[3 * u] = a[3 * u + 1] = a[3 * u + 2] = 1e18f;
-    }
     Cand c[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
         c[u] = test_pair<HAS_EMIN>(xj, yj, zj, a[3 * u], a[3 * u + 1], a[3 * u + 2], p);
-        if (SELF) c[u].acc = c[u].acc & (jcmp > ib + k + u);
+        if (SELF) c[u].acc = c[u].acc && (jrel > k + u);
     }
-    // ballots before any branch keep the four distance chains together
+    // ballots before any branch keep the four distance chains together; one
+    // ballot per compare (each is the compare's own lane mask), combined on
+    // the scalar unit
     unsigned long long bal[4];
 #pragma unroll
-    for (int u = 0; u < 4; u++) bal[u] = __builtin_amdgcn_ballot_w64(c[u].acc);
+    for (int u = 0; u < 4; u++) {
+        unsigned long long b = __builtin_amdgcn_ballot_w64(c[u].d2 < p.emax2_hi);
+        if (HAS_EMIN) b &= __builtin_amdgcn_ballot_w64(c[u].d2 >= p.emin2_lo);
+        if (SELF) b &= __builtin_amdgcn_ballot_w64(jrel > k + u);
+        if (TAIL && k + u >= n_i) b = 0;
+        bal[u] = b;
+    }
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(k + u), bal[u], qt, p, e2tab);
+        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(k + u), bal[u], qt, p, xt);
     return qt;
 }
 
@@ -304,54 +393,67 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
 // The chunk's 768 bytes stay in the scalar cache while every j block of the
 // chunk sweeps them.
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF>
-__device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int64_t jcmp,
+__device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int jrel,
                                             const float* __restrict__ pts, int64_t ib, int n_i,
-                                            const PcParams& p, const int64_t* __restrict__ e2tab) {
+                                            const PcParams& p, const ExactTab* __restrict__ xt) {
     ib = uniform64(ib);
     uint32_t qt = w.qtail;
     int k = 0;
     for (; k + 4 <= n_i; k += 4)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jcmp, pts + 3 * (ib + k), ib, k,
-                                                              n_i, qt, p, e2tab);
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), ib, k,
+                                                              n_i, qt, p, xt);
     if (k < n_i)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jcmp, pts + 3 * (ib + k), ib, k,
-                                                             n_i, qt, p, e2tab);
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), ib, k,
+                                                             n_i, qt, p, xt);
     w.qtail = qt;
 }
 
 template <int LOS, bool UNIFORM, bool HAS_EMIN>
 __global__ __launch_bounds__(512) void k_pair_count(
     const float* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
-    const int32_t* __restrict__ order, const int4* __restrict__ sten, const int64_t* __restrict__ e2tab,
+    const int32_t* __restrict__ order, const int4* __restrict__ sten, const ExactTab* __restrict__ xt,
     const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
     unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    // LDS: [histogram, hist_stride words][control, 4 words][midpoint i table,
+    // 64 x 3 words][one queue of kQ entries per wave]
     const int lane = threadIdx.x & 63;
-    const int wid = threadIdx.x >> 6;
-    unsigned char* wb = smem + size_t(wid) * p.wave_bytes;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int nwave = blockDim.x >> 6;
+    unsigned* ctl = reinterpret_cast<unsigned*>(smem) + p.hist_stride;
     WaveState w;
-    w.hist = reinterpret_cast<unsigned*>(wb);
-    w.qa = reinterpret_cast<float4*>(wb + size_t(p.hist_stride) * 4);
-    w.itab = reinterpret_cast<int*>(w.qa + kQ);
+    w.hist = reinterpret_cast<unsigned*>(smem);
+    w.itab = reinterpret_cast<int*>(ctl + 4);
+    w.qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
+    w.qa = reinterpret_cast<float4*>(smem + w.qbyte);
     w.qtail = 0;
     w.since_flush = 0;
     w.n_cand = 0;
     w.n_exact = w.n_flush = 0;
-    w.cur_task = -1;
-    for (int b = lane; b < p.hist_stride; b += 64) w.hist[b] = 0;
-    wave_sync_lds();
+    for (int b = threadIdx.x; b < p.hist_stride; b += blockDim.x) w.hist[b] = 0;
 
+    // work items are taken by the whole block (thread 0 pops, the others read
+    // the item from LDS), so the block's waves always count the same task
     int xq = int(blockIdx.x % kXcd);
     int exhausted = 0;
+    int cur_task = -1;
     for (;;) {
-        unsigned item = 0;
-        if (lane == 0) item = p.qstart[xq] + atomicAdd(&queue[xq], 1u);
-        item = __builtin_amdgcn_readfirstlane(item);
-        if (item >= p.qstart[xq + 1]) {
-            if (++exhausted == kXcd) break;
-            xq = (xq + 1) % kXcd;
-            continue;
+        __syncthreads();  // the previous item is done everywhere; ctl is free
+        if (threadIdx.x == 0) {
+            unsigned it = 0xFFFFFFFFu;
+            while (exhausted < kXcd) {
+                const unsigned v = p.qstart[xq] + atomicAdd(&queue[xq], 1u);
+                if (v < p.qstart[xq + 1]) {
+                    it = v;
+                    break;
+                }
+                ++exhausted;
+                xq = (xq + 1) % kXcd;
+            }
+            ctl[0] = it;
         }
+        __syncthreads();
+        const unsigned item = __builtin_amdgcn_readfirstlane(ctl[0]);
+        if (item == 0xFFFFFFFFu) break;
         int task, g;
         if (p.single_task >= 0) {
             task = p.single_task;
@@ -361,10 +463,16 @@ __global__ __launch_bounds__(512) void k_pair_count(
             g = int(item % unsigned(p.items_per_task));
         }
         task = __builtin_amdgcn_readfirstlane(task);
-        if (task != w.cur_task) {
-            if (w.cur_task >= 0) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
-            w.cur_task = task;
+        if (task != cur_task) {
+            if (cur_task >= 0) {
+                if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
+                block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
+                if (threadIdx.x == 0) w.n_flush++;
+            }
+            w.since_flush = 0;
+            cur_task = task;
         }
+        unsigned long long* const dst = counts + int64_t(task) * p.nbins;
         const int2 tk = tasks[task];
         const bool autop = tk.x == tk.y;
         const int64_t abase = int64_t(tk.x) * p.ncell, bbase = int64_t(tk.y) * p.ncell;
@@ -384,26 +492,36 @@ __global__ __launch_bounds__(512) void k_pair_count(
             if (ia0 == ia1) continue;
             const int cx = c % nx, cy = (c / nx) % ny, cz = c / (nx * ny);
             const int oix = ox[cx], oiy = oy[cy], oiz = oz[cz];
-            for (int64_t ib = ia0; ib < ia1; ib += 64) {
-                // i chunk: one point per lane (i cell frame); lanes past it hold
-                // a sentinel on the opposite side from the j sentinel
-                const int64_t gi = ib + lane;
-                const bool valid = gi < ia1;
-                float xi = 1e18f, yi = 1e18f, zi = 1e18f;
-                if (valid) {
-                    xi = pts[3 * gi];
-                    yi = pts[3 * gi + 1];
-                    zi = pts[3 * gi + 2];
-                    if (LOS == 1) {
-                        w.itab[3 * lane] = int(xi) + oix;
-                        w.itab[3 * lane + 1] = int(yi) + oiy;
-                        w.itab[3 * lane + 2] = int(zi) + oiz;
+            for (int64_t ib = ia0; ib < ia1; ib += p.chunk) {
+                // i chunk: points ib .. ib + n_i - 1 of the i cell; its bounding
+                // box from one point per lane per slice of 64
+                const int n_i = int(min(int64_t(p.chunk), ia1 - ib));
+                float blx = 3e38f, bly = 3e38f, blz = 3e38f;
+                float bhx = -3e38f, bhy = -3e38f, bhz = -3e38f;
+                for (int s0 = 0; s0 < n_i; s0 += 64) {
+                    if (lane < n_i - s0) {
+                        const int64_t gi = ib + s0 + lane;
+                        const float xi = pts[3 * gi], yi = pts[3 * gi + 1], zi = pts[3 * gi + 2];
+                        blx = fminf(blx, xi);
+                        bly = fminf(bly, yi);
+                        blz = fminf(blz, zi);
+                        bhx = fmaxf(bhx, xi);
+                        bhy = fmaxf(bhy, yi);
+                        bhz = fmaxf(bhz, zi);
                     }
                 }
-                const int n_i = int(min(int64_t(64), ia1 - ib));
-                // bounding box of the chunk's points
-                float blx = valid ? xi : 3e38f, bly = valid ? yi : 3e38f, blz = valid ? zi : 3e38f;
-                float bhx = valid ? xi : -3e38f, bhy = valid ? yi : -3e38f, bhz = valid ? zi : -3e38f;
+                if (LOS == 1) {
+                    // the block's i table (chunks of at most 64 points here):
+                    // every wave has binned the entries that refer to the last one
+                    __syncthreads();
+                    if (wid == 0 && lane < n_i) {
+                        const int64_t gi = ib + lane;
+                        w.itab[3 * lane] = int(pts[3 * gi]) + oix;
+                        w.itab[3 * lane + 1] = int(pts[3 * gi + 1]) + oiy;
+                        w.itab[3 * lane + 2] = int(pts[3 * gi + 2]) + oiz;
+                    }
+                    __syncthreads();
+                }
                 for (int o = 32; o > 0; o >>= 1) {
                     blx = fminf(blx, __shfl_xor(blx, o));
                     bly = fminf(bly, __shfl_xor(bly, o));
@@ -427,21 +545,25 @@ __global__ __launch_bounds__(512) void k_pair_count(
                         yj = pts[3 * jb_pend.idx + 1] + jb_pend.oy;
                         zj = pts[3 * jb_pend.idx + 2] + jb_pend.oz;
                     }
-                    const int64_t jcmp = (vj && jb_pend.self) ? jb_pend.idx : INT64_MAX;
+                    // self block: j index relative to the chunk start (pairs i < j
+                    // only; i indices within the chunk are below 64, so clamping
+                    // large offsets keeps every comparison)
+                    const int jrel = (vj && jb_pend.self) ? int(min(jb_pend.idx - ib, int64_t(INT_MAX))) : INT_MAX;
                     const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
                     w.n_cand += nc;
-                    // a uint32 histogram bin holds at most the candidate tests
-                    // since the last flush: flush before that bound could reach 2^32
-                    if (w.since_flush + nc >= 0xFFFFFFFFull) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
-                    w.since_flush += nc;
+                    // keep this wave's share of the bound on every bin (nc <= 2^14)
+                    if (w.since_flush + uint32_t(nc) >= p.wave_limit)
+                        wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
+                    w.since_flush += uint32_t(nc);
                     if (__builtin_amdgcn_ballot_w64(vj && jb_pend.self))
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jcmp, pts, ib, n_i, p,
-                                                                  e2tab);
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, pts, ib, n_i, p,
+                                                                  xt);
                     else
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jcmp, pts, ib, n_i, p,
-                                                                   e2tab);
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, pts, ib, n_i, p,
+                                                                   xt);
                 };
-                for (int s = 0; s < ns; ++s) {
+                // the block's waves share the stencil offsets of the chunk
+                for (int s = wid; s < ns; s += nwave) {
                     const int4 o = sten[s];
                     int jx = cx + o.x, jy = cy + o.y, jz = cz + o.z;
                     int shx = 0, shy = 0, shz = 0;
@@ -513,19 +635,25 @@ __global__ __launch_bounds__(512) void k_pair_count(
                 }
                 if (fill > 0) process(fill);
                 // midpoint entries refer to this chunk's i table: bin them before it changes
-                if (LOS == 1 && w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, e2tab);
+                if (LOS == 1 && w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
             }
         }
     }
-    if (w.cur_task >= 0) flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, e2tab, counts);
-    if (stats && lane == 0) {
-        atomicAdd(&stats[0], (unsigned long long)w.n_cand);
-        atomicAdd(&stats[2], (unsigned long long)w.n_exact);
-        atomicAdd(&stats[3], (unsigned long long)w.n_flush);
+    if (cur_task >= 0) {
+        if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
+        block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
+        if (threadIdx.x == 0) w.n_flush++;
+    }
+    if (stats) {
+        if (w.n_exact) atomicAdd(&stats[2], (unsigned long long)w.n_exact);
+        if (lane == 0) {
+            atomicAdd(&stats[0], (unsigned long long)w.n_cand);
+            atomicAdd(&stats[3], (unsigned long long)w.n_flush);
+        }
     }
 }
 
-typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_t*, const int4*, const int64_t*,
+typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_t*, const int4*, const ExactTab*,
                          const int32_t*, unsigned long long*, unsigned long long*, unsigned*, PcParams);
 
 static PcKernel pick_kernel(int los, bool uniform, bool has_emin) {
@@ -617,22 +745,26 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.n_r = n_r;
     p.n_mu = n_mu;
     p.nbins = n_r * n_mu;
-    p.hist_stride = (p.nbins + 3) & ~3;
+    p.hist_stride = (p.nbins + 1 + 3) & ~3;  // + the discard slot
     const bool mid = b->los == LC_LOS_MID;
-    p.wave_bytes = p.hist_stride * 4 + kQ * 16 + (mid ? 64 * 12 : 0);
+    const int max_chunk = mid ? 64 : 256;  // midpoint: the i table holds 64 points
+    // default: a whole cell per gather of its j points (fewer, larger chunks
+    // cost a few more candidate tests but gather j points less often)
+    const int chunk = tune && tune->chunk > 0 ? tune->chunk : max_chunk;
+    if (chunk > max_chunk || chunk % 4 != 0)
+        return fail(LC_ERR_INVALID, "chunk = %d, must be a multiple of 4 in [4, %d]", chunk, max_chunk);
+    p.chunk = chunk;
+    p.queue_byte0 = (p.hist_stride * 4 + 16 + (mid ? 64 * 12 : 0) + 15) & ~15;
     const int64_t e0 = b->r_edges[0];
     const int64_t de = int64_t(b->r_edges[1]) - b->r_edges[0];
     bool uniform = true;
     for (int k = 0; k <= n_r; k++)
         if (int64_t(b->r_edges[k]) != e0 + int64_t(k) * de) uniform = false;
-    p.emin2 = e0 * e0;
-    p.emax2 = rmax * rmax;
+    const int64_t emin2 = e0 * e0, emax2 = rmax * rmax;
     // phase A acceptance: the float32 squared distance is within 3 * 2^-24
     // (relative) of the exact one, inside the 2^-20 margins used here
-    p.emax2_hi = f32_up(double(p.emax2) * (1.0 + std::ldexp(1.0, -20)));
-    p.emin2_lo = f32_down(double(p.emin2) * (1.0 - std::ldexp(1.0, -20)));
-    p.e0 = e0;
-    p.de = de;
+    p.emax2_hi = f32_up(double(emax2) * (1.0 + std::ldexp(1.0, -20)));
+    p.emin2_lo = f32_down(double(emin2) * (1.0 - std::ldexp(1.0, -20)));
     p.inv_drf = float(1.0 / double(de));
     p.e0_over_drf = float(double(e0) / double(de));
     p.nmuf = float(n_mu);
@@ -649,14 +781,15 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     const double u = std::ldexp(1.0, -24);
     const double em = (mid ? 10.0 : 5.5) * u * n_mu;
     p.eps_m = f32_up(std::max(4.0 * em, std::ldexp(1.0, -22)));
-    p.nmu_m1_eps = f32_up(double(n_mu - 1) + double(p.eps_m));
     const double er = u * ((5.5 * double(rmax) + double(e0)) / double(de) + double(n_r));
     // plus the distance of an accepted pair outside [e_0, e_n) from the edge:
     // phase A accepts d2 < e_n^2 (1 + 2^-20) and d2 >= e_0^2 (1 - 2^-20), i.e.
     // |r - edge| < 2^-20 edge, which is at most 2^-20 r_max / de in units of t
     const double margin_t = std::ldexp(double(rmax) / double(de), -20);
     p.eps_r = f32_up(std::max(4.0 * er + 2.0 * margin_t, std::ldexp(1.0, -22)));
-    p.force_exact = (mode & LC_FORCE_EXACT) ? 1 : 0;
+    // LC_FORCE_EXACT: no fraction lies in (eps_r, 1 - eps_r) once eps_r >= 1,
+    // so every pair takes the integer rule
+    if (mode & LC_FORCE_EXACT) p.eps_r = 2.0f;
     const bool has_emin = e0 > 0;
     pl.kern = pick_kernel(mid ? 1 : 0, uniform, has_emin);
     pl.mode = mode;
@@ -665,9 +798,11 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     int wpb = tune && tune->waves_per_block > 0 ? tune->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8)
         return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4 or 8", wpb);
-    while (wpb > 1 && size_t(wpb) * p.wave_bytes > ctx->max_lds_block) wpb >>= 1;
+    while (wpb > 1 && size_t(p.queue_byte0) + size_t(wpb) * kQ * 16 > ctx->max_lds_block) wpb >>= 1;
     pl.threads = wpb * 64;
-    pl.lds = size_t(wpb) * p.wave_bytes;
+    pl.lds = size_t(p.queue_byte0) + size_t(wpb) * kQ * 16;
+    // each wave's share of the 2^32 bound on a histogram bin
+    p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
     if (pl.lds > ctx->max_lds_block)
         return fail(LC_ERR_INVALID, "histogram of %d bins does not fit in LDS", p.nbins);
     if (pl.lds > 65536) {
@@ -703,13 +838,11 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
         for (int x = 1; x <= kXcd; x++) p.qstart[x] = uint32_t(p.items_per_task);
         pl.n_queue = n_tasks * kXcd;
         pl.task_blocks.resize(n_tasks);
-        for (int t = 0; t < n_tasks; t++) {
-            int64_t need = (p.items_per_task + wpb - 1) / wpb;
-            pl.task_blocks[t] = int(std::max<int64_t>(1, std::min<int64_t>(need, pl.blocks)));
-        }
+        for (int t = 0; t < n_tasks; t++)
+            pl.task_blocks[t] = int(std::max<int64_t>(1, std::min<int64_t>(p.items_per_task, pl.blocks)));
     } else {
         // split the ordered tasks into kXcd contiguous ranges of equal cost;
-        // waves of XCD x start on range x and move on when it is empty
+        // blocks of XCD x start on range x and move on when it is empty
         double total = 0;
         for (int t = 0; t < n_tasks; t++) total += cost[t];
         p.qstart[0] = 0;
@@ -725,6 +858,20 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     // staged block: tasks, order, stencil, squared edges, zeroed queue counters
     std::vector<int64_t> e2(n_r + 1);
     for (int k = 0; k <= n_r; k++) e2[k] = int64_t(b->r_edges[k]) * int64_t(b->r_edges[k]);
+    std::vector<unsigned char> xtab(offsetof(ExactTab, e2) + sizeof(int64_t) * e2.size());
+    {
+        ExactTab head;
+        std::memset(&head, 0, sizeof head);
+        head.emin2 = emin2;
+        head.emax2 = emax2;
+        head.e0 = e0;
+        head.de = de;
+        head.n_r = n_r;
+        head.n_mu = n_mu;
+        head.discard = p.nbins;
+        std::memcpy(xtab.data(), &head, offsetof(ExactTab, e2));
+        std::memcpy(xtab.data() + offsetof(ExactTab, e2), e2.data(), sizeof(int64_t) * e2.size());
+    }
     std::vector<unsigned> qz(pl.n_queue, 0u);
     auto put = [&](const void* src, size_t bytes) {
         size_t off = (pl.blob.size() + 255) & ~size_t(255);
@@ -735,7 +882,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     pl.off_tasks = put(tasks, sizeof(lc_task) * n_tasks);
     pl.off_order = put(order.data(), sizeof(int32_t) * n_tasks);
     pl.off_sten = put(sten.data(), sizeof(int4) * sten.size());
-    pl.off_e2 = put(e2.data(), sizeof(int64_t) * e2.size());
+    pl.off_e2 = put(xtab.data(), xtab.size());
     // integer origin of every cell index along x, y and z
     std::vector<int32_t> ot;
     for (int a = 0; a < 3; a++)
@@ -750,7 +897,7 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
     const int2* d_tasks = reinterpret_cast<const int2*>(dev + pl.off_tasks);
     const int32_t* d_order = reinterpret_cast<const int32_t*>(dev + pl.off_order);
     const int4* d_sten = reinterpret_cast<const int4*>(dev + pl.off_sten);
-    const int64_t* d_e2 = reinterpret_cast<const int64_t*>(dev + pl.off_e2);
+    const ExactTab* d_e2 = reinterpret_cast<const ExactTab*>(dev + pl.off_e2);
     const int32_t* d_ot = reinterpret_cast<const int32_t*>(dev + pl.off_otab);
     unsigned* d_q = reinterpret_cast<unsigned*>(dev + pl.off_queue);
     auto* c = reinterpret_cast<unsigned long long*>(counts);

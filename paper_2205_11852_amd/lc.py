@@ -54,7 +54,7 @@ class lc_task(ctypes.Structure):
 
 class lc_tuning(ctypes.Structure):
     _fields_ = [("cells_per_item", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
 class lc_mesh_opts(ctypes.Structure):
@@ -232,7 +232,7 @@ def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int
     tn = None
     if tune:
         tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
-                       int(tune.get("blocks_per_cu", 0)), 0)
+                       int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)))
     _check(lib().lc_pair_count_batch(cells.handle if cells else None, t.ctypes.data, len(t),
                                      ctypes.byref(binning.c), _dptr(counts), int(mode),
                                      ctypes.byref(tn) if tn is not None else None, _dptr(stats),

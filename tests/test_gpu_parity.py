@@ -89,7 +89,9 @@ def test_c1_per_mock_baseline_identical(c1, torch):
 
 
 @pytest.mark.parametrize("tune", [dict(cells_per_item=1), dict(cells_per_item=7, waves_per_block=1),
-                                  dict(waves_per_block=8, blocks_per_cu=1), dict(waves_per_block=2)])
+                                  dict(waves_per_block=8, blocks_per_cu=1), dict(waves_per_block=2),
+                                  dict(chunk=4), dict(chunk=12), dict(chunk=32), dict(chunk=64),
+                                  dict(chunk=20, cells_per_item=3), dict(chunk=128), dict(chunk=256)])
 def test_c1_tunings_identical(c1, torch, tune):
     pl = c1["pl"]
     _say("[c1] tune", tune)
