@@ -408,8 +408,10 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
     w.qtail = qt;
 }
 
+// Six waves per SIMD (80 VGPRs): latency hiding pays more than the few
+// registers this spills outside the inner loops.
 template <int LOS, bool UNIFORM, bool HAS_EMIN>
-__global__ __launch_bounds__(512) void k_pair_count(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
     const float* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
     const int32_t* __restrict__ order, const int4* __restrict__ sten, const ExactTab* __restrict__ xt,
     const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
