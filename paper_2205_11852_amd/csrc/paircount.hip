@@ -39,6 +39,7 @@
 namespace lc {
 
 constexpr int kQ = 128;     // entries of the per-wave compaction queue
+constexpr int kX = 128;     // entries of the per-wave queue of pairs for the integer rule
 constexpr int kXcd = 8;     // queues (one per XCD)
 
 struct PcParams {
@@ -181,6 +182,8 @@ struct WaveState {
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
     int* itab;            // midpoint: absolute coordinates of the chunk's i points (block)
+    float4* xa;           // this wave's queue of pairs for the integer rule, entries [0, xn)
+    uint32_t xn;          // wave-uniform
     uint32_t qtail;       // wave-uniform
     uint32_t since_flush; // candidate tests this wave registered since its last flush
     uint64_t n_cand;
@@ -197,18 +200,16 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Histogram slot of one queued pair (the discard slot when it is dropped).
-// The float estimates are kept only when farther than eps from every edge;
-// the clamps to >= 1 make d2 = 0 and q = 0 produce estimates that fail that
-// test, so every value stays finite.  (eps_r >= 1 sends every pair to the
-// integer rule.)
+// Histogram slot of one queued pair from its float32 estimates.  They are
+// kept only when farther than eps from every edge (ok); otherwise the pair
+// takes the integer rule later.  d2 = 0 (and q = 0) give NaN or clamped
+// estimates that fail the test, so every value stays finite.  (eps_r >= 1
+// sends every pair to the integer rule.)
 template <int LOS, bool UNIFORM, bool HAS_E0>
-__device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__ itab, const PcParams& p,
-                                         const ExactTab* __restrict__ xt, uint32_t& n_exact) {
+__device__ __forceinline__ int bin_fast(const float4 e, const int* __restrict__ itab, const PcParams& p,
+                                        bool& ok) {
     float d2f, u;
-    double P = 0.0, Q = 0.0;
     if (LOS == 0) {
-        // d2 = 0 gives rsq = inf and NaN estimates, which fail the edge test
         d2f = e.w;
         u = fabsf(e.z) * __builtin_amdgcn_rsqf(d2f) * p.nmuf;
     } else {
@@ -218,17 +219,17 @@ __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__
         const double lx = 2.0 * double(itab[3 * il]) + double(e.x);
         const double ly = 2.0 * double(itab[3 * il + 1]) + double(e.y);
         const double lz = 2.0 * double(itab[3 * il + 2]) + double(e.z);
-        P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
-        Q = fma(lx, lx, fma(ly, ly, lz * lz));
+        const double P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
+        const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
         d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
         u = fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)) *
             p.nmuf;
     }
     // |mu| n_mu <= n_mu exactly; an estimate at or above n_mu - eps_m (mu near
-    // 1) fails the test below and takes the integer rule, so m < n_mu here
+    // 1) fails the test below, so m < n_mu whenever ok
     const int m = int(u);
     const float fm = __builtin_amdgcn_fractf(u);
-    bool ok = (fm > p.eps_m) & (fm < 1.0f - p.eps_m);
+    ok = (fm > p.eps_m) & (fm < 1.0f - p.eps_m);
     int k = 0;
     if (UNIFORM) {
         // eps_r also covers phase A's acceptance margin, so a pair outside
@@ -241,31 +242,88 @@ __device__ __forceinline__ int bin_entry(const float4 e, const int* __restrict__
     } else {
         ok = false;  // non-uniform edges: every pair takes the integer rule
     }
-    if (!ok) {
-        n_exact++;
-        if (LOS == 0) return exact_bin_z<UNIFORM>(double(e.x), double(e.y), double(e.z), k, m, xt);
-        return exact_bin<LOS, UNIFORM>(int64_t(int(e.x)), int64_t(int(e.y)), int64_t(int(e.z)), int64_t(P),
-                                       uint64_t(Q), k, m, xt);
-    }
     // 24-bit multiply: k < n_r and n_mu are far below 2^24
     return int(__umul24(uint32_t(k), uint32_t(p.n_mu))) + m;
 }
 
+// Histogram slot of one queued pair by the integer rule (discard slot when it
+// lies outside [e_0, e_n)); the float64 estimates only seed the searches.
+template <int LOS, bool UNIFORM>
+__device__ __forceinline__ int exact_entry(const float4 e, const int* __restrict__ itab,
+                                           const ExactTab* __restrict__ xt) {
+    const double x = e.x, y = e.y, z = e.z;
+    const double d2 = fma(x, x, fma(y, y, z * z));
+    const double r = sqrt(d2);
+    const int k_est = UNIFORM ? int((r - double(xt->e0)) / double(xt->de)) : 0;
+    if (LOS == 0) {
+        const int m_est = d2 > 0.0 ? int(fabs(z) / r * double(xt->n_mu)) : 0;
+        return exact_bin_z<UNIFORM>(x, y, z, k_est, m_est, xt);
+    }
+    const int il = __float_as_int(e.w);
+    const double lx = 2.0 * double(itab[3 * il]) + x;
+    const double ly = 2.0 * double(itab[3 * il + 1]) + y;
+    const double lz = 2.0 * double(itab[3 * il + 2]) + z;
+    const double P = fma(x, lx, fma(y, ly, z * lz));
+    const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
+    const int m_est = (d2 > 0.0 && Q > 0.0) ? int(fabs(P) / sqrt(d2 * Q) * double(xt->n_mu)) : 0;
+    return exact_bin<LOS, UNIFORM>(int64_t(int(e.x)), int64_t(int(e.y)), int64_t(int(e.z)), int64_t(P),
+                                   uint64_t(Q), k_est, m_est, xt);
+}
+
+// Bin the last n (<= 64) of the xn pairs waiting for the integer rule, one
+// per lane with every lane busy.  Returns the new length.
+template <int LOS, bool UNIFORM>
+__device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t n, uint32_t xn,
+                                                const ExactTab* __restrict__ xt) {
+    wave_sync_lds();
+    const uint32_t first = xn - n;
+    if (uint32_t(lane) < n) {
+        const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], w.itab, xt);
+        __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        w.n_exact++;
+    }
+    wave_sync_lds();
+    return __builtin_amdgcn_readfirstlane(first);
+}
+
 // Bin the last n (<= 64) of the qt queued pairs, one per lane (the queue is
-// an unordered bag, so taking from its end leaves the rest in place).
-// Returns the new queue length.
+// an unordered bag, so taking from its end leaves the rest in place).  Pairs
+// the estimates cannot decide move to the integer-rule queue, which is binned
+// 64 at a time.  Returns the new queue length.
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = qt - n;
+    float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    bool ok = true;
     if (uint32_t(lane) < n) {
-        const float4 e = w.qa[first + lane];
-        const int bin = bin_entry<LOS, UNIFORM, HAS_E0>(e, w.itab, p, xt, w.n_exact);
-        __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        e = w.qa[first + lane];
+        const int bin = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.itab, p, ok);
+        if (ok) __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    const unsigned long long xb = __builtin_amdgcn_ballot_w64(!ok);
+    if (xb) {
+        uint32_t xn = __builtin_amdgcn_readfirstlane(w.xn);
+        if (!ok) {
+            const uint32_t rank =
+                __builtin_amdgcn_mbcnt_hi(uint32_t(xb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(xb), 0u));
+            w.xa[xn + rank] = e;
+        }
+        xn = __builtin_amdgcn_readfirstlane(xn + uint32_t(__popcll(xb)));
+        if (xn >= 64) xn = drain_exact<LOS, UNIFORM>(w, lane, 64, xn, xt);
+        w.xn = xn;
     }
     wave_sync_lds();
     return __builtin_amdgcn_readfirstlane(first);
+}
+
+// Bin everything this wave has queued (both queues).
+template <int LOS, bool UNIFORM, bool HAS_E0>
+__device__ __forceinline__ void drain_all(WaveState& w, int lane, const PcParams& p,
+                                          const ExactTab* __restrict__ xt) {
+    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, xt);
+    if (w.xn) w.xn = drain_exact<LOS, UNIFORM>(w, lane, w.xn, w.xn, xt);
 }
 
 // Every bin value is at most the sum over the block's waves of the candidate
@@ -278,7 +336,7 @@ template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ void wave_flush(WaveState& w, int lane, const PcParams& p,
                                            const ExactTab* __restrict__ xt,
                                            unsigned long long* __restrict__ dst) {
-    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, xt);
+    drain_all<LOS, UNIFORM, HAS_E0>(w, lane, p, xt);
     for (int b = lane; b < p.nbins; b += 64) {
         const unsigned v = __hip_atomic_exchange(&w.hist[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (v) __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -417,7 +475,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
     const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
     unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
     // LDS: [histogram, hist_stride words][control, 4 words][midpoint i table,
-    // 64 x 3 words][one queue of kQ entries per wave]
+    // 64 x 3 words][one queue of kQ entries per wave][one integer-rule queue
+    // of kX entries per wave]
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
@@ -427,6 +486,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
     w.itab = reinterpret_cast<int*>(ctl + 4);
     w.qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
     w.qa = reinterpret_cast<float4*>(smem + w.qbyte);
+    w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kX;
+    w.xn = 0;
     w.qtail = 0;
     w.since_flush = 0;
     w.n_cand = 0;
@@ -467,7 +528,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
         task = __builtin_amdgcn_readfirstlane(task);
         if (task != cur_task) {
             if (cur_task >= 0) {
-                if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
+                drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
                 block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
                 if (threadIdx.x == 0) w.n_flush++;
             }
@@ -637,12 +698,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k
                 }
                 if (fill > 0) process(fill);
                 // midpoint entries refer to this chunk's i table: bin them before it changes
-                if (LOS == 1 && w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
+                if (LOS == 1) drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
             }
         }
     }
     if (cur_task >= 0) {
-        if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_EMIN>(w, lane, w.qtail, w.qtail, p, xt);
+        drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
         block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
         if (threadIdx.x == 0) w.n_flush++;
     }
@@ -800,9 +861,9 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     int wpb = tune && tune->waves_per_block > 0 ? tune->waves_per_block : 4;
     if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8)
         return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4 or 8", wpb);
-    while (wpb > 1 && size_t(p.queue_byte0) + size_t(wpb) * kQ * 16 > ctx->max_lds_block) wpb >>= 1;
+    while (wpb > 1 && size_t(p.queue_byte0) + size_t(wpb) * (kQ + kX) * 16 > ctx->max_lds_block) wpb >>= 1;
     pl.threads = wpb * 64;
-    pl.lds = size_t(p.queue_byte0) + size_t(wpb) * kQ * 16;
+    pl.lds = size_t(p.queue_byte0) + size_t(wpb) * (kQ + kX) * 16;
     // each wave's share of the 2^32 bound on a histogram bin
     p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
     if (pl.lds > ctx->max_lds_block)
