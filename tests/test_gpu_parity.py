@@ -169,13 +169,20 @@ def test_xi_multipoles_parity(c1, oracle_mod, torch):
 
 @pytest.fixture(scope="module")
 def c1_cov(c1, oracle_mod, torch):
+    """Oracle data vectors (from the oracle's counts) and their LC matrices.
+    The covariance tests feed the same vectors to the device, so the stage is
+    compared on identical inputs."""
     pl = c1["pl"]
-    pl.count()
-    pl.xi_multipoles()
-    torch.cuda.synchronize()
-    xi = pl.xi.cpu().numpy()
-    A, B, C, Ca, Cb = oracle_mod.lc_from_vectors(xi, 1, 50.0)
-    return dict(xi=xi, A=A, B=B, C=C)
+    counts = c1["ref"]
+    V = np.stack([oracle_mod.mock_vectors(*(counts[t] for t in pl.est[m]), pl.sizes[pl.tasks[pl.est[m][0]][0]],
+                                          pl.sizes[pl.tasks[pl.est[m][1]][1]], pl.sizes[pl.tasks[pl.est[m][2]][1]])
+                  for m in range(pl.n_mock)])
+    A, B, C, Ca, Cb = oracle_mod.lc_from_vectors(V, 1, 50.0)
+    return dict(xi=V, A=A, B=B, C=C)
+
+
+def _load_xi(pl, V, torch):
+    pl.xi.copy_(torch.from_numpy(np.ascontiguousarray(V)).to(pl.xi.device))
 
 
 def _rel_frob(x, y):
@@ -185,6 +192,7 @@ def _rel_frob(x, y):
 
 def test_covariance_fp64_parity(c1, c1_cov, lcmod, torch):
     pl = c1["pl"]
+    _load_xi(pl, c1_cov["xi"], torch)
     for M in (50.0, 1.0, 2.0, float("inf")):
         pl.covariance(lcmod.LC_FP64, report=False, M=M)
         torch.cuda.synchronize()
@@ -199,6 +207,7 @@ def test_covariance_fp64_parity(c1, c1_cov, lcmod, torch):
 
 def test_covariance_fp32_mfma_parity(c1, c1_cov, lcmod, torch):
     pl = c1["pl"]
+    _load_xi(pl, c1_cov["xi"], torch)
     rep = pl.covariance(lcmod.LC_FP32_MFMA_CHECKED, report=True)
     torch.cuda.synchronize()
     A, B, C = (t.cpu().numpy() for t in (pl.A, pl.B, pl.C))
