@@ -7,7 +7,7 @@ covariances with the float64 linear construction and its Cholesky/eigenvalue
 check.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--config c2]
-                    [--no-cpu] [--no-per-mock]
+                    [--no-cpu] [--no-per-mock] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -76,6 +76,8 @@ def main():
     ap.add_argument("--no-per-mock", action="store_true")
     ap.add_argument("--cell-mpc", type=float, default=0.0)
     ap.add_argument("--sub", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-sample", type=int, default=64, help="tasks timed by the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this path has no multi-GPU mode "
@@ -98,6 +100,13 @@ def main():
     pl = Pipeline(cats)
     cell_units = int(args.cell_mpc * mockgen.UNITS_PER_MPC)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not args.no_autotune and cell_units == 0 and args.sub == 0:
+        # mesh and launch shape chosen by timing a sample of the tasks (once,
+        # outside the timed region; the library caches the choice)
+        t0 = time.perf_counter()
+        tuned = pl.autotune(args.tune_sample)
+        log("[bench] autotune: %s (%.1f s)" % (json.dumps(tuned), time.perf_counter() - t0))
 
     def step(events=None):
         pl.build_cells(cell_units, args.sub)
@@ -149,7 +158,8 @@ def main():
                                "%d x %d randoms, %d r-bins to %g Mpc/h x %d mu-bins, %s line of sight"
                                % (wl.name, n_mock, wl.n_mean, wl.box_mpc, wl.n_subsets, wl.subset_size,
                                   wl.n_r, wl.r_max_mpc, wl.n_mu, wl.los),
-                   "n_tasks": int(len(pl.tasks)), "cells": pl.cells.info()["grid"]},
+                   "n_tasks": int(len(pl.tasks)), "cells": pl.cells.info()["grid"],
+                   "sub_cells": pl.cells.info()["sub"], "autotuned": tuned},
         "pair_tests_per_s": cand / kern_s,
         "binned_pairs_per_s": binned / kern_s,
         "pair_count_ms": float(np.mean(count_ms)),

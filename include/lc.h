@@ -217,8 +217,42 @@ lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n
                         int32_t m_a, double M, int32_t precision,
                         double* A, double* B, double* C, lc_cov_report* rep, void* stream);
 
-/* Release cached device buffers, graphs and pinned staging memory of the
- * current device (they are otherwise kept until the process ends). */
+/* Result of lc_autotune: the mesh options and launch tuning to use. */
+typedef struct {
+    int32_t cell_units;       /* for lc_mesh_opts.cell_units */
+    int32_t sub;              /* for lc_mesh_opts.sub */
+    lc_tuning tune;           /* for lc_pair_count_batch */
+    double sample_ms;         /* time of one launch over the sampled tasks */
+    int32_t n_tried;          /* configurations timed */
+    int32_t sample_tasks;     /* tasks in the sample */
+    int32_t cached;           /* 1: returned from the cache, nothing was timed */
+    int32_t reserved;
+} lc_autotune_result;
+
+/*
+ * lc_autotune: choose the mesh (cell side, sub-cell split) and the launch
+ * shape (i points per gather) for a batch of tasks by timing them.
+ * Pair counts do not depend on these choices (they are exact); only the time
+ * does, through the number of candidate tests and the cost of gathering
+ * neighbour cells.  Candidates: cell sides r_max / k (k = 1, 1.5, 2, 3, 4) and
+ * the default, each with sub-cell splits 1, 2 and 4; then chunks of i points
+ * for the best mesh.  Each is timed with HIP events over `sample_tasks` tasks
+ * spread evenly over the list (one untimed launch, then two timed).
+ *   xyz, n_total, cat_offsets, n_cat, b   as for lc_build_cells.
+ *   tasks     HOST [n_tasks], as for lc_pair_count_batch.
+ *   sample_tasks  tasks to time (<= 0: 64).
+ *   out       HOST, written.
+ * Synchronises `stream` (blocking call).  The result is cached per device
+ * and configuration (binning, catalogue sizes, task list, sample size) until
+ * lc_release_caches; a cached call times nothing.
+ */
+lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets, int32_t n_cat,
+                      const lc_binning* b, const lc_task* tasks, int32_t n_tasks, int32_t sample_tasks,
+                      void* stream, lc_autotune_result* out);
+
+/* Release cached device buffers, graphs, autotuning results and pinned
+ * staging memory of the current device (they are otherwise kept until the
+ * process ends). */
 void lc_release_caches(void);
 
 #ifdef __cplusplus

@@ -1,0 +1,215 @@
+// Autotuner for the mesh and the pair-count launch.
+//
+// Pair counting is exact for every mesh and launch shape; only the time
+// changes.  The cost is (candidate tests) x (per-test work) + (cost of
+// gathering the neighbour cells), and both terms move in opposite directions
+// with the cell side, the sub-cell split and the chunk of i points tested per
+// gather.  Rather than model that trade on a given catalogue set, the tuner
+// measures it: it builds candidate meshes, times the persistent launch on an
+// evenly spread sample of the tasks with HIP events, and keeps the fastest.
+// Results are cached per device and configuration for the life of the process.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+namespace {
+
+std::mutex g_tune_mu;
+std::map<std::string, lc_autotune_result> g_tune_cache;
+
+void mix(uint64_t& h, uint64_t v) {  // FNV-1a over the 8 bytes of v
+    for (int i = 0; i < 8; i++) {
+        h ^= (v >> (8 * i)) & 0xFF;
+        h *= 1099511628211ull;
+    }
+}
+
+std::string tune_key(int device, const lc_binning* b, const int64_t* off, int32_t n_cat, const lc_task* tasks,
+                     int32_t n_tasks, int32_t sample) {
+    uint64_t h = 1469598103934665603ull;
+    mix(h, uint64_t(b->periodic));
+    mix(h, uint64_t(b->box_units));
+    mix(h, uint64_t(b->los));
+    mix(h, uint64_t(b->n_r));
+    mix(h, uint64_t(b->n_mu));
+    for (int k = 0; k <= b->n_r; k++) mix(h, uint64_t(b->r_edges[k]));
+    mix(h, uint64_t(n_cat));
+    for (int32_t c = 0; c <= n_cat; c++) mix(h, uint64_t(off[c]));
+    mix(h, uint64_t(n_tasks));
+    for (int32_t t = 0; t < n_tasks; t++) mix(h, (uint64_t(uint32_t(tasks[t].cat_a)) << 32) | uint32_t(tasks[t].cat_b));
+    mix(h, uint64_t(sample));
+    char buf[64];
+    std::snprintf(buf, sizeof buf, "%d:%016llx", device, (unsigned long long)h);
+    return buf;
+}
+
+// Time `reps` launches of the sample (after one untimed launch); ms per launch.
+lc_status time_launch(const lc_cells* cells, const std::vector<lc_task>& sample, const lc_binning* b,
+                      uint64_t* counts, const lc_tuning& tune, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                      int reps, double* ms) {
+    const int32_t n = int32_t(sample.size());
+    LC_TRY(lc_pair_count_batch(cells, sample.data(), n, b, counts, LC_PERSISTENT, &tune, nullptr, s));
+    LC_TRY_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; r++)
+        LC_TRY(lc_pair_count_batch(cells, sample.data(), n, b, counts, LC_PERSISTENT, &tune, nullptr, s));
+    LC_TRY_HIP(hipEventRecord(e1, s));
+    LC_TRY_HIP(hipEventSynchronize(e1));
+    float t = 0.0f;
+    LC_TRY_HIP(hipEventElapsedTime(&t, e0, e1));
+    *ms = double(t) / reps;
+    return LC_OK;
+}
+
+}  // namespace
+
+void release_tuning() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache.clear();
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets, int32_t n_cat,
+                                 const lc_binning* b, const lc_task* tasks, int32_t n_tasks, int32_t sample_tasks,
+                                 void* stream, lc_autotune_result* out) {
+    clear_error();
+    if (!out) return fail(LC_ERR_INVALID, "out is NULL");
+    std::memset(out, 0, sizeof *out);
+    LC_TRY(check_binning(b));
+    if (n_tasks < 1) return fail(LC_ERR_INVALID, "n_tasks = %d, must be >= 1", n_tasks);
+    if (!tasks) return fail(LC_ERR_INVALID, "tasks is NULL");
+    if (!cat_offsets) return fail(LC_ERR_INVALID, "cat_offsets is NULL");
+    if (n_cat < 1) return fail(LC_ERR_INVALID, "n_cat = %d, must be >= 1", n_cat);
+    if (sample_tasks < 1) sample_tasks = 64;
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    hipStream_t s = (hipStream_t)stream;
+    const std::string key = tune_key(ctx->device, b, cat_offsets, n_cat, tasks, n_tasks, sample_tasks);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            *out = it->second;
+            out->cached = 1;
+            return LC_OK;
+        }
+    }
+
+    // evenly spread sample of the tasks (the task list of a batch repeats
+    // the same few task types mock after mock)
+    std::vector<lc_task> sample;
+    const int32_t ns = std::min(n_tasks, sample_tasks);
+    for (int32_t i = 0; i < ns; i++) sample.push_back(tasks[int64_t(i) * n_tasks / ns]);
+
+    const int64_t rmax = b->r_edges[b->n_r];
+    const bool mid = b->los == LC_LOS_MID;
+    const int nbins = b->n_r * b->n_mu;
+    uint64_t* counts = nullptr;
+    LC_TRY(dev_alloc((void**)&counts, size_t(ns) * nbins * sizeof(uint64_t), s));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    lc_status st = LC_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        st = fail(LC_ERR_HIP, "hipEventCreate failed");
+
+    // candidate cell sides: r_max / k (k = 1 .. 4) and the library default,
+    // distinct by the grid they give along the longest axis
+    lc_autotune_result best{};
+    best.sample_ms = 1e300;
+    int tried = 0;
+    std::vector<int32_t> grids;
+    std::vector<int32_t> widths;
+    if (st == LC_OK) {
+        lc_cells* c0 = nullptr;
+        lc_mesh_opts o0{};
+        st = lc_build_cells(xyz, n_total, cat_offsets, n_cat, b, &o0, s, &c0);
+        if (st == LC_OK) {
+            lc_cells_info inf;
+            lc_cells_get_info(c0, &inf);
+            double ext = 0.0;
+            for (int a = 0; a < 3; a++) ext = std::max(ext, double(inf.grid[a]) * inf.cell_side[a]);
+            std::vector<double> ws = {inf.cell_side[0]};
+            for (double k : {1.0, 1.5, 2.0, 3.0, 4.0}) ws.push_back(double(rmax) / k);
+            for (double w : ws) {
+                const int32_t wu = int32_t(std::max(1.0, std::floor(w)));
+                const int32_t n = int32_t(std::max(1.0, std::floor(ext / wu)));
+                if (std::find(grids.begin(), grids.end(), n) != grids.end()) continue;
+                grids.push_back(n);
+                widths.push_back(wu);
+            }
+            lc_free_cells(c0);
+        }
+    }
+    // stage 1: mesh (cell side x sub-cell split) at the default launch shape
+    const int chunk0 = mid ? 64 : 256;
+    lc_mesh_opts best_mesh{};
+    for (size_t iw = 0; iw < widths.size() && st == LC_OK; iw++) {
+        for (int sub : {1, 2, 4}) {
+            lc_mesh_opts o{};
+            o.cell_units = widths[iw];
+            o.sub = sub;
+            lc_cells* c = nullptr;
+            st = lc_build_cells(xyz, n_total, cat_offsets, n_cat, b, &o, s, &c);
+            if (st != LC_OK) break;
+            lc_tuning tn{};
+            tn.chunk = chunk0;
+            double ms = 0.0;
+            st = time_launch(c, sample, b, counts, tn, s, e0, e1, 2, &ms);
+            lc_free_cells(c);
+            if (st != LC_OK) break;
+            tried++;
+            if (ms < best.sample_ms) {
+                best.sample_ms = ms;
+                best_mesh = o;
+                best.tune = tn;
+            }
+        }
+    }
+    // stage 2: chunk of i points per gather on the chosen mesh
+    if (st == LC_OK) {
+        lc_cells* c = nullptr;
+        st = lc_build_cells(xyz, n_total, cat_offsets, n_cat, b, &best_mesh, s, &c);
+        if (st == LC_OK) {
+            const std::vector<int> chunks = mid ? std::vector<int>{32, 64} : std::vector<int>{64, 128, 256};
+            for (int ch : chunks) {
+                if (ch == chunk0) continue;
+                lc_tuning tn{};
+                tn.chunk = ch;
+                double ms = 0.0;
+                st = time_launch(c, sample, b, counts, tn, s, e0, e1, 2, &ms);
+                if (st != LC_OK) break;
+                tried++;
+                if (ms < best.sample_ms) {
+                    best.sample_ms = ms;
+                    best.tune = tn;
+                }
+            }
+            lc_free_cells(c);
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    dev_free(counts, s);
+    if (st != LC_OK) return st;
+    best.cell_units = best_mesh.cell_units;
+    best.sub = best_mesh.sub;
+    best.n_tried = tried;
+    best.sample_tasks = ns;
+    best.cached = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = best;
+    }
+    *out = best;
+    return LC_OK;
+}

@@ -127,4 +127,8 @@ lc_status check_binning(const lc_binning* b);
 // negative half.  Offsets whose cells cannot hold a pair closer than r_max
 // are pruned.  Returns n_half (self + positive half).
 int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out);
+
+// Drop the cached pair-count graphs and autotuning results.
+void release_graphs();
+void release_tuning();
 }  // namespace lc

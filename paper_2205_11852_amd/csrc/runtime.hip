@@ -120,6 +120,8 @@ extern "C" const char* lc_last_error(void) { return lc::g_err.c_str(); }
 extern "C" void lc_release_caches(void) {
     lc::DeviceCtx* c = nullptr;
     if (lc::get_ctx(&c) != LC_OK) return;
+    lc::release_graphs();
+    lc::release_tuning();
     std::lock_guard<std::mutex> lk(c->mu);
     if (c->pinned_pending) (void)hipEventSynchronize(c->pinned_ev);
     c->pinned_pending = false;

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ER
 
 # the exported symbols of include/lc.h
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
-           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_release_caches"]
+           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_autotune", "lc_release_caches"]
 
 
 class LcLibraryMissing(RuntimeError):
@@ -67,6 +67,20 @@ class lc_cells_info(ctypes.Structure):
                 ("cell_side", ctypes.c_double * 3), ("sub", ctypes.c_int32),
                 ("reserved", ctypes.c_int32), ("n_total", ctypes.c_int64),
                 ("bytes", ctypes.c_int64)]
+
+
+class lc_autotune_result(ctypes.Structure):
+    _fields_ = [("cell_units", ctypes.c_int32), ("sub", ctypes.c_int32), ("tune", lc_tuning),
+                ("sample_ms", ctypes.c_double), ("n_tried", ctypes.c_int32), ("sample_tasks", ctypes.c_int32),
+                ("cached", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        t = self.tune
+        return {"cell_units": self.cell_units, "sub": self.sub,
+                "tune": {"cells_per_item": t.cells_per_item, "waves_per_block": t.waves_per_block,
+                         "blocks_per_cu": t.blocks_per_cu, "chunk": t.chunk},
+                "sample_ms": self.sample_ms, "n_tried": self.n_tried, "sample_tasks": self.sample_tasks,
+                "cached": bool(self.cached)}
 
 
 class lc_cov_report(ctypes.Structure):
@@ -109,6 +123,9 @@ def lib():
     L.lc_covariance.restype = st
     L.lc_covariance.argtypes = [vp, i32, i32, i32, i32, ctypes.c_double, i32, vp, vp, vp,
                                 ctypes.POINTER(lc_cov_report), vp]
+    L.lc_autotune.restype = st
+    L.lc_autotune.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning), vp, i32, i32, vp,
+                              ctypes.POINTER(lc_autotune_result)]
     L.lc_release_caches.restype = None
     L.lc_release_caches.argtypes = []
     _lib = L
@@ -255,6 +272,18 @@ def lc_covariance(xi, n_mock: int, n_r: int, n_mu: int, m_a: int, M: float, prec
                                int(precision), _dptr(A), _dptr(B), _dptr(C),
                                ctypes.byref(rep) if rep is not None else None, _stream(stream)))
     return rep.as_dict() if rep is not None else None
+
+
+def lc_autotune(xyz, cat_offsets, binning: Binning, tasks, sample_tasks: int = 0, stream=None) -> dict:
+    """Time candidate meshes and launch shapes; returns the chosen mesh
+    options (cell_units, sub) and tuning dict (blocking)."""
+    off = np.ascontiguousarray(np.asarray(cat_offsets, dtype=np.int64))
+    t = tasks_array(tasks)
+    res = lc_autotune_result()
+    _check(lib().lc_autotune(_dptr(xyz), int(off[-1]) if len(off) else 0, off.ctypes.data, len(off) - 1,
+                             ctypes.byref(binning.c), t.ctypes.data, len(t), int(sample_tasks),
+                             _stream(stream), ctypes.byref(res)))
+    return res.as_dict()
 
 
 def lc_release_caches():

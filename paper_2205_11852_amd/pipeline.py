@@ -65,11 +65,20 @@ class Pipeline:
         self.C = torch.empty((P, P), dtype=torch.float64, device=device)
         self.cells: Optional[lc.Cells] = None
         self._nb = nb
+        self.tuned: Optional[dict] = None
 
     # -- steps ---------------------------------------------------------------
+    def autotune(self, sample_tasks: int = 0) -> dict:
+        """Pick the mesh and launch shape by timing (cached by the library);
+        later build_cells() and count() calls without explicit options use it."""
+        self.tuned = lc.lc_autotune(self.xyz, self.offsets, self.binning, self.tasks, sample_tasks)
+        return self.tuned
+
     def build_cells(self, cell_units: int = 0, sub: int = 0):
         if self.cells is not None:
             self.cells.close()
+        if self.tuned is not None and cell_units == 0 and sub == 0:
+            cell_units, sub = self.tuned["cell_units"], self.tuned["sub"]
         self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units, sub)
         return self.cells
 
@@ -77,6 +86,8 @@ class Pipeline:
         if zero:
             self.counts.zero_()
             self.stats.zero_()
+        if tune is None and self.tuned is not None:
+            tune = self.tuned["tune"]
         lc.lc_pair_count_batch(self.cells, self.tasks, self.binning, self.counts, mode, tune,
                                self.stats)
 
@@ -84,6 +95,8 @@ class Pipeline:
         """Baseline: one launch per task, mock after mock, synchronising after
         each mock (shared RR counted once, before the loop)."""
         torch = self.torch
+        if tune is None and self.tuned is not None:
+            tune = self.tuned["tune"]
         self.counts.zero_()
         self.stats.zero_()
         nbytes = self._nb * 8

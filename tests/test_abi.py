@@ -135,3 +135,17 @@ def test_covariance_rejects_bad_arguments(L, args, code):
 
 def test_last_error_is_thread_local_string(L):
     assert isinstance(lc.last_error(), str)
+
+
+def test_autotune_rejects_bad_arguments(L):
+    b = _binning()
+    off = np.array([0, 4], dtype=np.int64)
+    t = np.array([[0, 0]], dtype=np.int32)
+    res = lc.lc_autotune_result()
+    assert L.lc_autotune(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), t.ctypes.data, 1, 8, None,
+                         None) == lc.LC_ERR_INVALID
+    assert L.lc_autotune(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), t.ctypes.data, 0, 8, None,
+                         ctypes.byref(res)) == lc.LC_ERR_INVALID
+    assert L.lc_autotune(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), None, 1, 8, None,
+                         ctypes.byref(res)) == lc.LC_ERR_INVALID
+    assert "tasks" in lc.last_error()

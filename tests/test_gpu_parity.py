@@ -100,6 +100,21 @@ def test_c1_tunings_identical(c1, torch, tune):
     assert np.array_equal(pl.counts_host(), c1["ref"])
 
 
+def test_c1_autotuned_counts_identical(c1, torch):
+    """The autotuner's choice counts the same pairs; a second call is cached."""
+    pl = c1["pl"]
+    res = pl.autotune(16)
+    _say("[c1] autotune", res)
+    assert res["n_tried"] > 3 and not res["cached"] and res["sample_ms"] > 0
+    assert pl.autotune(16)["cached"]
+    pl.build_cells()
+    pl.count()
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.counts_host(), c1["ref"])
+    pl.tuned = None
+    pl.build_cells()
+
+
 @pytest.mark.parametrize("cell_mpc,sub", [(25.0, 1), (33.0, 2), (50.0, 4), (100.0, 1), (100.0, 2),
                                           (100.0, 4), (160.0, 4), (240.0, 4)])
 def test_c1_cell_sizes_identical(c1, torch, cell_mpc, sub):
