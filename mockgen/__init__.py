@@ -267,21 +267,23 @@ def make_catalogues(wl: Workload, n_mock: Optional[int] = None) -> Catalogues:
     return Catalogues(wl, np.ascontiguousarray(xyz, dtype=np.int32), offsets, n_mock, randoms)
 
 
-def independent_poisson_mocks(cfg_id: int, n_mock: int, n_points: int,
-                              box_units: int) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
-    """Uniform ("random") mocks with their own R1, R2 of the same size.
+def independent_poisson_mocks(cfg_id: int, n_mock: int, n_points: int, box_units: int,
+                              n_random: int = 2) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Uniform ("random") mocks with their own random sub-catalogues of the
+    same size (n_random of them: R1, R2, ...).
 
     Mirrors the paper's random-mock test (Sect. 4.2): data are themselves
     uniform with a fixed size, and every realisation has independent
     random catalogues.  Returns xyz int32 [3, n_total], offsets, and the
-    (n_mock, 3) catalogue ids (D, R1, R2).
+    (n_mock, 1 + n_random) catalogue ids (D, R1, R2, ...).
     """
-    cats, ids = [], np.zeros((n_mock, 3), dtype=np.int64)
+    k = 1 + n_random
+    cats, ids = [], np.zeros((n_mock, k), dtype=np.int64)
     for m in range(n_mock):
-        for r in range(3):
+        for r in range(k):
             ids[m, r] = len(cats)
             cats.append(uniform_box(rng_for(cfg_id, ROLE_DATA if r == 0 else ROLE_RANDOM,
-                                            3 * m + r), n_points, box_units))
+                                            k * m + r), n_points, box_units))
     sizes = np.array([c.shape[1] for c in cats], dtype=np.int64)
     offsets = np.zeros(len(cats) + 1, dtype=np.int64)
     np.cumsum(sizes, out=offsets[1:])
