@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--cell-mpc", type=float, default=0.0)
     ap.add_argument("--sub", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--direct-mocks", type=int, default=8,
+                    help="mocks timed for the direct estimate over every random sub-catalogue (0: skip)")
     ap.add_argument("--tune-sample", type=int, default=64, help="tasks timed by the autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -209,6 +211,39 @@ def main():
         out["batched_vs_per_mock_c1"] = {"workload": "c1", "batched_s": float(np.median(ts)),
                                          "per_mock_s": float(np.median(tp)),
                                          "speedup": float(np.median(tp) / np.median(ts))}
+
+    if args.direct_mocks > 0 and not cats.wl.per_mock_randoms:
+        # The cost the linear construction avoids (Sect. 2.3, Table 3): the
+        # direct split estimate over all M random sub-catalogues needs DD and M
+        # DR per mock (plus each RR once), against DD, DR1, DR2 for LC.
+        from paper_2205_11852_amd.pipeline import plan_direct_tasks
+        subsets = cats.random_catalogue_ids()
+        M = len(subsets)
+        nd = min(args.direct_mocks, n_mock)
+        log("[bench] direct estimate: %d mocks x M = %d" % (nd, M))
+        tasks_d, _ = plan_direct_tasks(range(nd), subsets)
+        parts = {"rr": tasks_d[:M], "dd_dr": tasks_d[M:]}
+        t_ms = {}
+        for key, tk in parts.items():
+            cd = torch.zeros((len(tk), pl.binning.n_r, pl.binning.n_mu), dtype=torch.int64, device="cuda")
+            tune = pl.tuned["tune"] if pl.tuned else None
+            lc.lc_pair_count_batch(pl.cells, tk, pl.binning, cd, lc.LC_PERSISTENT, tune, None)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            lc.lc_pair_count_batch(pl.cells, tk, pl.binning, cd, lc.LC_PERSISTENT, tune, None)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t_ms[key] = e0.elapsed_time(e1)
+            del cd
+        direct = t_ms["dd_dr"] / 1e3 / nd + t_ms["rr"] / 1e3 / n_mock
+        lc_mock = kern_s / n_mock
+        nbar = float(np.mean(pl.sizes[:n_mock]))
+        ns = float(wl.subset_size)
+        model = (0.5 * nbar * nbar + M * nbar * ns) / (0.5 * nbar * nbar + 2 * nbar * ns)
+        out["direct_vs_lc"] = {"M": M, "mocks_timed": nd, "direct_pair_count_s_per_mock": direct,
+                               "lc_pair_count_s_per_mock": lc_mock, "ratio": direct / lc_mock,
+                               "pair_ratio_model": model,
+                               "note": "RR of the shared sub-catalogues amortised over all mocks in both"}
 
     if not args.no_cpu:
         import oracle

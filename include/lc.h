@@ -217,6 +217,37 @@ lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n
                         int32_t m_a, double M, int32_t precision,
                         double* A, double* B, double* C, lc_cov_report* rep, void* stream);
 
+/*
+ * lc_xi_split: one split Landy-Szalay estimate per mock with M = n_sub random
+ * sub-catalogues (the estimator whose sample covariance the linear
+ * construction predicts, Sect. 2.1-2.3), with its multipoles; float64.
+ *   counts, tasks, cat_sizes  as for lc_xi_multipoles.
+ *   est     HOST int32 [n_mock][1 + 2 n_sub]: task ids of DD, DR_1 .. DR_M,
+ *           RR_1 .. RR_M; DD = (D,D), DR_i = (D,R_i), RR_i = (R_i,R_i), R_i != D.
+ *   xi      DEVICE double [n_mock][P], P = n_r*n_mu + 3*n_r, written (layout as
+ *           one estimate of lc_xi_multipoles).
+ * Same normalisation and estimator as lc_xi_multipoles, the sums over
+ * subsets taken in the order given; with n_sub = 2 it reproduces that call's
+ * third estimate.  Errors: LC_ERR_INVALID for inconsistent task ids or
+ * n_sub outside [1, 4096].  Asynchronous.
+ */
+lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, int32_t n_tasks,
+                      const int64_t* cat_sizes, int32_t n_cat, const int32_t* est, int32_t n_sub,
+                      int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, void* stream);
+
+/*
+ * lc_sample_covariance: the sample covariance over mocks of one estimate
+ * (Sect. 2.2): C = sum_n (x_n - mean)(x_n - mean)^T / (N - 1), two-pass.
+ *   x          DEVICE double [n_mock][P] (e.g. from lc_xi_split); n_mock >= 2.
+ *   precision  LC_FP64, or LC_FP32_MFMA (float32 deviations, MFMA products
+ *              accumulated in float32 over blocks of 256 mocks and summed in
+ *              float64).
+ *   C          DEVICE double [P][P], written (full symmetric).
+ * Asynchronous; NaN entries propagate to their rows and columns.
+ */
+lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32_t P, int32_t precision, double* C,
+                               void* stream);
+
 /* Result of lc_autotune: the mesh options and launch tuning to use. */
 typedef struct {
     int32_t cell_units;       /* for lc_mesh_opts.cell_units */

@@ -45,24 +45,24 @@ __global__ void k_mean_final(const double* __restrict__ partial, int64_t nchunk,
     mean[j] = s / double(n_mock);
 }
 
-// dev64[e][n][p] = xi[n][e][p] - mean[e][p]    (ld = P)
+// dev64[e][n][p] = xi[n][e][p] - mean[e][p]    (ne estimates per mock; ld = P)
 __global__ void k_dev64(const double* __restrict__ xi, const double* __restrict__ mean, int64_t n_mock,
-                        int64_t P, double* __restrict__ dev) {
-    const int64_t tot = 3 * n_mock * P;
+                        int64_t P, int64_t ne, double* __restrict__ dev) {
+    const int64_t tot = ne * n_mock * P;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int64_t p = t % P;
         const int64_t r = t / P;
         const int64_t n = r % n_mock;
         const int64_t e = r / n_mock;
-        dev[t] = xi[n * 3 * P + e * P + p] - mean[e * P + p];
+        dev[t] = xi[n * ne * P + e * P + p] - mean[e * P + p];
     }
 }
 
 // dev32[e][n][p] (ld = Ppad, Npad rows, zero padded) = float(xi - mean)
 __global__ void k_dev32(const double* __restrict__ xi, const double* __restrict__ mean, int64_t n_mock,
-                        int64_t P, int64_t Npad, int64_t Ppad, float* __restrict__ dev) {
-    const int64_t tot = 3 * Npad * Ppad;
+                        int64_t P, int64_t ne, int64_t Npad, int64_t Ppad, float* __restrict__ dev) {
+    const int64_t tot = ne * Npad * Ppad;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < tot;
          t += int64_t(gridDim.x) * blockDim.x) {
         const int64_t p = t % Ppad;
@@ -70,7 +70,7 @@ __global__ void k_dev32(const double* __restrict__ xi, const double* __restrict_
         const int64_t n = r % Npad;
         const int64_t e = r / Npad;
         float v = 0.0f;
-        if (n < n_mock && p < P) v = float(xi[n * 3 * P + e * P + p] - mean[e * P + p]);
+        if (n < n_mock && p < P) v = float(xi[n * ne * P + e * P + p] - mean[e * P + p]);
         dev[t] = v;
     }
 }
@@ -627,7 +627,7 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
     auto run_fp64 = [&](double* covbuf) -> lc_status {
         double* dev = nullptr;
         LC_TRY(dev_alloc((void**)&dev, sizeof(double) * 3 * N * P, s));
-        k_dev64<<<nblocks(3 * N * P, 256, 65536), 256, 0, s>>>(xi, mean, N, P, dev);
+        k_dev64<<<nblocks(3 * N * P, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, dev);
         k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 3), 256, 0, s>>>(dev, N, P, denom, covbuf);
         dev_free(dev, s);
         return LC_OK;
@@ -637,7 +637,7 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
         const int64_t Ppad = (P + kMT - 1) / kMT * kMT;
         float* dev = nullptr;
         LC_TRY(dev_alloc((void**)&dev, sizeof(float) * 3 * Npad * Ppad, s));
-        k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, Npad, Ppad, dev);
+        k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, Npad, Ppad, dev);
         const int64_t T = Ppad / kMT;
         k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev, Npad, Ppad, P, denom, covbuf);
         dev_free(dev, s);
@@ -696,5 +696,53 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
     }
     if (!A) dev_free(Aw, s);
     if (!B) dev_free(Bw, s);
+    return LC_OK;
+}
+
+extern "C" lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32_t P, int32_t precision, double* C,
+                                          void* stream) {
+    clear_error();
+    if (!x || !C) return fail(LC_ERR_INVALID, "x and C must not be NULL");
+    if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
+    if (P < 1 || P > 4 * LC_MAX_BINS) return fail(LC_ERR_INVALID, "P = %d out of range", P);
+    if (precision != LC_FP64 && precision != LC_FP32_MFMA)
+        return fail(LC_ERR_INVALID, "precision = %d is not LC_FP64 / LC_FP32_MFMA", precision);
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    (void)ctx;
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t N = n_mock, PL = P;
+    const double denom = double(N - 1);
+    double* mean = nullptr;
+    double* part = nullptr;
+    LC_TRY(dev_alloc((void**)&mean, sizeof(double) * PL, s));
+    const int64_t nchunk = (N + kMeanRows - 1) / kMeanRows;
+    LC_TRY(dev_alloc((void**)&part, sizeof(double) * PL * nchunk, s));
+    {
+        dim3 g(unsigned((PL + 255) / 256), unsigned(nchunk));
+        k_mean_partial<<<g, 256, 0, s>>>(x, N, PL, part);
+        k_mean_final<<<unsigned((PL + 255) / 256), 256, 0, s>>>(part, nchunk, PL, N, mean);
+    }
+    if (precision == LC_FP64) {
+        double* dev = nullptr;
+        LC_TRY(dev_alloc((void**)&dev, sizeof(double) * N * PL, s));
+        k_dev64<<<nblocks(N * PL, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, dev);
+        const int64_t T64 = (PL + 63) / 64;
+        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 1), 256, 0, s>>>(dev, N, PL, denom, C);
+        dev_free(dev, s);
+    } else {
+        const int64_t Npad = (N + kKT - 1) / kKT * kKT;
+        const int64_t Ppad = (PL + kMT - 1) / kMT * kMT;
+        float* dev = nullptr;
+        LC_TRY(dev_alloc((void**)&dev, sizeof(float) * Npad * Ppad, s));
+        k_dev32<<<nblocks(Npad * Ppad, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, Npad, Ppad, dev);
+        const int64_t T = Ppad / kMT;
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 1), 256, 0, s>>>(dev, Npad, Ppad, PL, denom, C);
+        dev_free(dev, s);
+    }
+    hipError_t e = hipGetLastError();
+    dev_free(mean, s);
+    dev_free(part, s);
+    if (e != hipSuccess) return fail(LC_ERR_HIP, "covariance launch failed: %s", hipGetErrorString(e));
     return LC_OK;
 }

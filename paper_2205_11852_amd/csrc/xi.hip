@@ -58,6 +58,43 @@ __global__ void k_xi(const unsigned long long* __restrict__ counts, const int32_
         for (int l = 0; l < 3; l++) out[q * P + nb + int64_t(l) * n_r + k] = mp[q][l];
 }
 
+// One split estimate per mock with M random sub-catalogues (the sample
+// covariance's estimator, Sect. 2.1-2.2): est row = [DD, DR_1..DR_M,
+// RR_1..RR_M], norm row alike.  xi = (dd - (2/M) sum dr_i) / ((1/M) sum rr_i) + 1,
+// the sums taken in subset order.  Output [n_mock][P] (xi(r, mu) then the
+// multipoles).
+__global__ void k_xi_split(const unsigned long long* __restrict__ counts, const int32_t* __restrict__ est,
+                           const double* __restrict__ norm, const double* __restrict__ W, int32_t n_mock,
+                           int32_t n_sub, int32_t n_r, int32_t n_mu, double* __restrict__ xi) {
+#pragma clang fp contract(off)
+    const int64_t idx = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+    if (idx >= int64_t(n_mock) * n_r) return;
+    const int mk = int(idx / n_r), k = int(idx % n_r);
+    const int64_t nb = int64_t(n_r) * n_mu;
+    const int64_t P = nb + 3 * int64_t(n_r);
+    const int64_t w = 1 + 2 * int64_t(n_sub);
+    const int32_t* e = est + w * mk;
+    const double* nr = norm + w * mk;
+    const double two_over_m = 2.0 / double(n_sub), one_over_m = 1.0 / double(n_sub);
+    double* out = xi + int64_t(mk) * P;
+    double mp[3] = {0, 0, 0};
+    const double nan = __builtin_nan("");
+    for (int m = 0; m < n_mu; m++) {
+        const int64_t off = int64_t(k) * n_mu + m;
+        const double dd = double(counts[e[0] * nb + off]) / nr[0];
+        double sdr = 0.0, srr = 0.0;
+        for (int i = 0; i < n_sub; i++) {
+            sdr = sdr + double(counts[e[1 + i] * nb + off]) / nr[1 + i];
+            srr = srr + double(counts[e[1 + n_sub + i] * nb + off]) / nr[1 + n_sub + i];
+        }
+        const double den = one_over_m * srr;
+        const double x = den == 0.0 ? nan : (dd - two_over_m * sdr) / den + 1.0;
+        out[off] = x;
+        for (int l = 0; l < 3; l++) mp[l] = mp[l] + W[l * n_mu + m] * x;
+    }
+    for (int l = 0; l < 3; l++) out[nb + int64_t(l) * n_r + k] = mp[l];
+}
+
 // Integral of P_l from 0 to x, l = 0, 2, 4 (P_2 = (3x^2-1)/2, P_4 = (35x^4-30x^2+3)/8).
 static double legendre_integral(int l, double x) {
     const double x2 = x * x;
@@ -66,6 +103,18 @@ static double legendre_integral(int l, double x) {
         case 2: return 0.5 * x * (x2 - 1.0);
         default: return x * (x2 * (7.0 * x2 - 10.0) + 3.0) / 8.0;
     }
+}
+
+static std::vector<double> legendre_weights(int n_mu) {
+    std::vector<double> W(3 * size_t(n_mu));
+    for (int li = 0; li < 3; li++) {
+        const int l = 2 * li;
+        for (int m = 0; m < n_mu; m++) {
+            const double a = double(m) / n_mu, b = double(m + 1) / n_mu;
+            W[li * size_t(n_mu) + m] = (2 * l + 1) * (legendre_integral(l, b) - legendre_integral(l, a));
+        }
+    }
+    return W;
 }
 
 }  // namespace lc
@@ -109,14 +158,7 @@ extern "C" lc_status lc_xi_multipoles(const uint64_t* counts, const lc_task* tas
         nr[3] = double(n1 * (n1 - 1)) / 2.0;
         nr[4] = double(n2 * (n2 - 1)) / 2.0;
     }
-    std::vector<double> W(3 * size_t(n_mu));
-    for (int li = 0; li < 3; li++) {
-        const int l = 2 * li;
-        for (int m = 0; m < n_mu; m++) {
-            const double a = double(m) / n_mu, b = double(m + 1) / n_mu;
-            W[li * size_t(n_mu) + m] = (2 * l + 1) * (legendre_integral(l, b) - legendre_integral(l, a));
-        }
-    }
+    const std::vector<double> W = legendre_weights(n_mu);
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
     hipStream_t s = (hipStream_t)stream;
@@ -133,6 +175,67 @@ extern "C" lc_status lc_xi_multipoles(const uint64_t* counts, const lc_task* tas
         reinterpret_cast<const unsigned long long*>(counts), reinterpret_cast<const int32_t*>(base + o_est),
         reinterpret_cast<const double*>(base + o_norm), reinterpret_cast<const double*>(base + o_w), n_mock,
         n_r, n_mu, xi);
+    hipError_t e = hipGetLastError();
+    dev_free(dev, s);
+    if (e != hipSuccess) return fail(LC_ERR_HIP, "xi launch failed: %s", hipGetErrorString(e));
+    return LC_OK;
+}
+
+extern "C" lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, int32_t n_tasks,
+                                 const int64_t* cat_sizes, int32_t n_cat, const int32_t* est, int32_t n_sub,
+                                 int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, void* stream) {
+    clear_error();
+    if (n_mock < 0) return fail(LC_ERR_INVALID, "n_mock < 0");
+    if (n_mock == 0) return LC_OK;
+    if (!counts || !tasks || !cat_sizes || !est || !xi) return fail(LC_ERR_INVALID, "NULL argument");
+    if (n_sub < 1 || n_sub > 4096) return fail(LC_ERR_INVALID, "n_sub = %d out of [1, 4096]", n_sub);
+    if (n_r < 1 || n_mu < 1 || n_mu > LC_MAX_NMU || int64_t(n_r) * n_mu > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
+    if (n_tasks < 1 || n_cat < 1) return fail(LC_ERR_INVALID, "n_tasks and n_cat must be >= 1");
+    const size_t w = 1 + 2 * size_t(n_sub);
+    std::vector<double> norm(w * size_t(n_mock));
+    for (int32_t m = 0; m < n_mock; m++) {
+        const int32_t* e = est + w * size_t(m);
+        for (size_t q = 0; q < w; q++)
+            if (e[q] < 0 || e[q] >= n_tasks) return fail(LC_ERR_INVALID, "mock %d: task id %d out of range", m, e[q]);
+        const lc_task DD = tasks[e[0]];
+        const int32_t D = DD.cat_a;
+        if (DD.cat_b != D || D < 0 || D >= n_cat)
+            return fail(LC_ERR_INVALID, "mock %d: the first task is not DD = (D, D)", m);
+        const int64_t nd = cat_sizes[D];
+        if (nd < 2 || nd >= (int64_t(1) << 26))
+            return fail(LC_ERR_INVALID, "mock %d: data catalogue size %lld outside [2, 2^26)", m, (long long)nd);
+        double* nr = norm.data() + w * size_t(m);
+        nr[0] = double(nd * (nd - 1)) / 2.0;
+        for (int32_t i = 0; i < n_sub; i++) {
+            const lc_task DR = tasks[e[1 + i]], RR = tasks[e[1 + n_sub + i]];
+            const int32_t R = DR.cat_b;
+            if (DR.cat_a != D || R == D || R < 0 || R >= n_cat || RR.cat_a != R || RR.cat_b != R)
+                return fail(LC_ERR_INVALID, "mock %d subset %d: tasks are not DR = (D, R), RR = (R, R)", m, i);
+            const int64_t n1 = cat_sizes[R];
+            if (n1 < 2 || n1 >= (int64_t(1) << 26))
+                return fail(LC_ERR_INVALID, "mock %d subset %d: size %lld outside [2, 2^26)", m, i, (long long)n1);
+            nr[1 + i] = double(nd) * double(n1);
+            nr[1 + n_sub + i] = double(n1 * (n1 - 1)) / 2.0;
+        }
+    }
+    const std::vector<double> W = legendre_weights(n_mu);
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    hipStream_t s = (hipStream_t)stream;
+    void* dev = nullptr;
+    Stager stg(ctx);
+    size_t o_est = stg.push(est, sizeof(int32_t) * w * size_t(n_mock));
+    size_t o_norm = stg.push(norm.data(), sizeof(double) * norm.size());
+    size_t o_w = stg.push(W.data(), sizeof(double) * W.size());
+    LC_TRY(stg.commit(s, &dev));
+    auto* base = static_cast<unsigned char*>(dev);
+    const int64_t n = int64_t(n_mock) * n_r;
+    const int threads = 128;
+    k_xi_split<<<int((n + threads - 1) / threads), threads, 0, s>>>(
+        reinterpret_cast<const unsigned long long*>(counts), reinterpret_cast<const int32_t*>(base + o_est),
+        reinterpret_cast<const double*>(base + o_norm), reinterpret_cast<const double*>(base + o_w), n_mock,
+        n_sub, n_r, n_mu, xi);
     hipError_t e = hipGetLastError();
     dev_free(dev, s);
     if (e != hipSuccess) return fail(LC_ERR_HIP, "xi launch failed: %s", hipGetErrorString(e));

@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ER
 
 # the exported symbols of include/lc.h
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
-           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_autotune", "lc_release_caches"]
+           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance",
+           "lc_autotune", "lc_release_caches"]
 
 
 class LcLibraryMissing(RuntimeError):
@@ -123,6 +124,10 @@ def lib():
     L.lc_covariance.restype = st
     L.lc_covariance.argtypes = [vp, i32, i32, i32, i32, ctypes.c_double, i32, vp, vp, vp,
                                 ctypes.POINTER(lc_cov_report), vp]
+    L.lc_xi_split.restype = st
+    L.lc_xi_split.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, i32, vp, vp]
+    L.lc_sample_covariance.restype = st
+    L.lc_sample_covariance.argtypes = [vp, i32, i32, i32, vp, vp]
     L.lc_autotune.restype = st
     L.lc_autotune.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning), vp, i32, i32, vp,
                               ctypes.POINTER(lc_autotune_result)]
@@ -272,6 +277,21 @@ def lc_covariance(xi, n_mock: int, n_r: int, n_mu: int, m_a: int, M: float, prec
                                int(precision), _dptr(A), _dptr(B), _dptr(C),
                                ctypes.byref(rep) if rep is not None else None, _stream(stream)))
     return rep.as_dict() if rep is not None else None
+
+
+def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, xi, stream=None):
+    """est: [n_mock][1 + 2 n_sub] task ids (DD, DR_1..DR_M, RR_1..RR_M);
+    xi: float64 device tensor [n_mock, P]."""
+    t = tasks_array(tasks)
+    sz = np.ascontiguousarray(np.asarray(cat_sizes, dtype=np.int64))
+    e = np.ascontiguousarray(np.asarray(est, dtype=np.int32).reshape(-1, 1 + 2 * int(n_sub)))
+    _check(lib().lc_xi_split(_dptr(counts), t.ctypes.data, len(t), sz.ctypes.data, len(sz), e.ctypes.data,
+                             int(n_sub), len(e), int(n_r), int(n_mu), _dptr(xi), _stream(stream)))
+
+
+def lc_sample_covariance(x, n_mock: int, P: int, precision: int, C, stream=None):
+    _check(lib().lc_sample_covariance(_dptr(x), int(n_mock), int(P), int(precision), _dptr(C),
+                                      _stream(stream)))
 
 
 def lc_autotune(xyz, cat_offsets, binning: Binning, tasks, sample_tasks: int = 0, stream=None) -> dict:

@@ -37,6 +37,23 @@ def plan_tasks(n_mock: int, randoms: np.ndarray) -> Tuple[np.ndarray, np.ndarray
     return np.array(tasks, dtype=np.int32).reshape(-1, 2), est
 
 
+def plan_direct_tasks(mocks: Sequence[int], subsets: Sequence[int]) -> Tuple[np.ndarray, np.ndarray]:
+    """Task table and est rows for the direct estimate with every mock split
+    over the same M random sub-catalogues: [DD, DR_1..DR_M, RR_1..RR_M] per
+    mock; each RR_i is counted once for all mocks."""
+    tasks: List[Tuple[int, int]] = [(int(s), int(s)) for s in subsets]
+    rr = list(range(len(subsets)))
+    est = []
+    for m in mocks:
+        row = [len(tasks)]
+        tasks.append((int(m), int(m)))
+        for s in subsets:
+            row.append(len(tasks))
+            tasks.append((int(m), int(s)))
+        est.append(row + rr)
+    return np.array(tasks, dtype=np.int32).reshape(-1, 2), np.array(est, dtype=np.int32)
+
+
 class Pipeline:
     """Device-resident catalogues of one workload and the calls of the path."""
 
@@ -137,6 +154,22 @@ class Pipeline:
         self.count(mode, tune)
         self.xi_multipoles()
         return self.covariance(precision, report)
+
+    def direct_estimates(self, mocks: Sequence[int], subsets: Sequence[int], tune: Optional[dict] = None):
+        """The split estimate of each listed mock over all listed random
+        sub-catalogues (M = len(subsets)): counts every needed task in one
+        persistent launch on the current mesh, then lc_xi_split.  Returns
+        (x [len(mocks), P] device tensor, counts, tasks, est)."""
+        torch = self.torch
+        tasks, est = plan_direct_tasks(mocks, subsets)
+        b = self.binning
+        counts = torch.zeros((len(tasks), b.n_r, b.n_mu), dtype=torch.int64, device=self.device)
+        if tune is None and self.tuned is not None:
+            tune = self.tuned["tune"]
+        lc.lc_pair_count_batch(self.cells, tasks, b, counts, lc.LC_PERSISTENT, tune, None)
+        x = torch.empty((len(mocks), b.P), dtype=torch.float64, device=self.device)
+        lc.lc_xi_split(counts, tasks, self.sizes, est, len(subsets), b.n_r, b.n_mu, x)
+        return x, counts, tasks, est
 
     # -- host copies ---------------------------------------------------------
     def counts_host(self) -> np.ndarray:

@@ -149,3 +149,18 @@ def test_autotune_rejects_bad_arguments(L):
     assert L.lc_autotune(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), None, 1, 8, None,
                          ctypes.byref(res)) == lc.LC_ERR_INVALID
     assert "tasks" in lc.last_error()
+
+
+def test_xi_split_and_sample_covariance_reject_bad_arguments(L):
+    tasks = np.array([[0, 0], [0, 1], [1, 1]], dtype=np.int32)
+    sizes = np.array([10, 10], dtype=np.int64)
+    good = np.array([[0, 1, 2]], dtype=np.int32)
+    assert L.lc_xi_split(0x1000, tasks.ctypes.data, 3, sizes.ctypes.data, 2, good.ctypes.data, 0, 1, 3, 4,
+                         0x2000, None) == lc.LC_ERR_INVALID
+    swapped = np.array([[0, 2, 1]], dtype=np.int32)
+    assert L.lc_xi_split(0x1000, tasks.ctypes.data, 3, sizes.ctypes.data, 2, swapped.ctypes.data, 1, 1, 3, 4,
+                         0x2000, None) == lc.LC_ERR_INVALID
+    assert "subset" in lc.last_error()
+    assert L.lc_sample_covariance(0x1000, 1, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_sample_covariance(0x1000, 5, 10, 7, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_sample_covariance(None, 5, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID

@@ -342,3 +342,66 @@ def test_out_of_box_coordinate_is_an_error(torch, lcmod):
     with pytest.raises(lcmod.LcError) as ei:
         lcmod.lc_build_cells(big, [0, 1], lcmod.Binning([0, 10], 1, False, 0, lcmod.LC_LOS_MID))
     assert ei.value.status == lcmod.LC_ERR_RANGE
+
+
+def test_direct_split_estimate_and_sample_covariance(torch, oracle_mod, lcmod):
+    """The direct estimate with M = 6 random sub-catalogues per mock (the
+    sample covariance the linear construction replaces): counts bit-exact,
+    the split estimate to 1e-12, its sample covariance to 1e-12 (float64) and
+    1e-5 (float32 MFMA)."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    wl = dataclasses.replace(mockgen.WORKLOADS["c1"], n_mock=8, n_subsets=6, subset_size=3000)
+    cats = mockgen.make_catalogues(wl)
+    subsets = cats.random_catalogue_ids()
+    assert len(subsets) == 6
+    pl = Pipeline(cats)
+    pl.build_cells()
+    x, counts, tasks, est = pl.direct_estimates(range(cats.n_mock), subsets)
+    torch.cuda.synchronize()
+    got = counts.cpu().numpy().view(np.uint64)
+    ref = np.zeros_like(got)
+    for t, (a, b) in enumerate(tasks):
+        ref[t] = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units,
+                                        wl.n_mu, wl.box_units, wl.los)
+    assert np.array_equal(got, ref)
+    M = len(subsets)
+    V = []
+    for m in range(cats.n_mock):
+        e = est[m]
+        xs = oracle_mod.ls_split(ref[e[0]], [ref[t] for t in e[1:1 + M]], [ref[t] for t in e[1 + M:]],
+                                 pl.sizes[m], [pl.sizes[s] for s in subsets])
+        V.append(oracle_mod.data_vector(xs))
+    V = np.array(V)
+    g = x.cpu().numpy()
+    assert np.array_equal(np.isnan(g), np.isnan(V))
+    nb = wl.n_r * wl.n_mu
+    ok = np.isfinite(V)
+    assert np.allclose(g[:, :nb][ok[:, :nb]], V[:, :nb][ok[:, :nb]], rtol=1e-12, atol=0)
+    W = oracle_mod.legendre_weights(wl.n_mu)
+    for m in range(cats.n_mock):
+        x2 = V[m, :nb].reshape(wl.n_r, wl.n_mu)
+        scale = (np.abs(x2)[:, None, :] * np.abs(W)[None, :, :]).sum(axis=2).T.ravel()
+        fin = np.isfinite(V[m, nb:])
+        assert np.all(np.abs(g[m, nb:] - V[m, nb:])[fin] <= 1e-12 * scale[fin] + 1e-300)
+    # sample covariance of the oracle's own vectors, on the device
+    P = V.shape[1]
+    xv = torch.from_numpy(np.ascontiguousarray(V)).cuda()
+    C = torch.empty((P, P), dtype=torch.float64, device="cuda")
+    refC = oracle_mod.sample_cov(V)
+    for prec, tol in ((lcmod.LC_FP64, 1e-12), (lcmod.LC_FP32_MFMA, 1e-5)):
+        lcmod.lc_sample_covariance(xv, V.shape[0], P, prec, C)
+        torch.cuda.synchronize()
+        assert _rel_frob(C.cpu().numpy(), refC) < tol, prec
+
+
+def test_split_estimate_with_two_subsets_matches_xi_multipoles(c1, torch, lcmod):
+    """lc_xi_split over (R1, R2) is the third estimate of lc_xi_multipoles."""
+    pl = c1["pl"]
+    pl.count()
+    pl.xi_multipoles()
+    x = torch.empty((pl.n_mock, pl.binning.P), dtype=torch.float64, device="cuda")
+    lcmod.lc_xi_split(pl.counts, pl.tasks, pl.sizes, pl.est, 2, pl.binning.n_r, pl.binning.n_mu, x)
+    torch.cuda.synchronize()
+    a, b = x.cpu().numpy(), pl.xi[:, 2, :].cpu().numpy()
+    assert np.array_equal(np.isnan(a), np.isnan(b))
+    assert np.array_equal(a[np.isfinite(a)], b[np.isfinite(b)])
