@@ -19,13 +19,19 @@ Everything below is the plain definition from the paper, in float64:
   C^a = (Cov xi(D,R1) + Cov xi(D,R2)) / 2, C^b = Cov xi(D, R1 u R2),
   A = 2 C^b - C^a, B = 2 M_a (C^a - C^b), C^LC = A + B / M;
 * the positive-definiteness check the paper recommends for C^LC (Sect. 3):
-  Cholesky and the eigenvalue spectrum (numpy / LAPACK).
+  Cholesky and the eigenvalue spectrum (numpy / LAPACK);
+* the covariance of the covariance estimates for Gaussian data vectors
+  (Sect. 3.2, 3.3): element variances of the sample and of the LC
+  covariance, and their summaries chi^2_2, pair-count cost and inverse
+  figure of merit (Sect. 5.3, Table 3).
 
 Readings where the paper is silent (documented with the tests):
   mu is |mu| on [0, 1] with uniform bins, the last one closed at mu = 1;
   r bins are half-open [e_k, e_k+1); a pair at zero separation goes to mu
   bin 0; DR and RR are normalised by the actual sub-catalogue sizes; a bin
-  with rr = 0 gives xi = NaN.
+  with rr = 0 gives xi = NaN.  In the LC covariance of covariance, D is
+  A + B/(2 M_a) (the printed A + B/M_a does not reproduce the term-by-term
+  expansion), and the last term pairs B_il with B_jk.
 """
 from __future__ import annotations
 
@@ -216,6 +222,71 @@ def check_matrix(C: np.ndarray) -> Dict[str, float]:
     w = np.linalg.eigvalsh(C)
     return {"chol_ok": ok, "n_neg_eig": int((w < 0).sum()),
             "min_eig": float(w[0]), "max_eig": float(w[-1])}
+
+
+# ---------------------------------------------------------------------------
+# covariance of the covariance estimates (Sect. 3) and its summaries (Sect. 5.3)
+# ---------------------------------------------------------------------------
+
+def sample_cov_element_var(C: np.ndarray, n_mock: int) -> np.ndarray:
+    """Var of each element of the sample covariance for Gaussian estimates
+    (Sect. 3.2, the covariance of the sample covariance with k = i, l = j):
+    (C_ii C_jj + C_ij^2) / (N - 1)."""
+    d = np.diag(C)
+    return (np.outer(d, d) + C * C) / (n_mock - 1)
+
+
+def lc_d_matrix(A: np.ndarray, B: np.ndarray, m_a: int) -> np.ndarray:
+    """D = A + B / (2 M_a), the ensemble covariance at M = 2 M_a.  (The printed
+    definition A + B / M_a is inconsistent with the formula it enters: expanding
+    the LC covariance in the x, x' estimates term by term gives this D; the
+    tests check the expansion.)"""
+    return A + B / (2.0 * m_a)
+
+
+def lc_cov_element_var(A: np.ndarray, B: np.ndarray, m_a: int, M: float, n_mock: int) -> np.ndarray:
+    """Var of each element of C^LC(M) for Gaussian estimates (Sect. 3.3, the
+    covariance of the LC covariance with k = i, l = j):
+    (D_ii D_jj + D_ij^2 + (1/(2 M_a) - 1/M)^2 (B_ii B_jj + B_ij^2)) / (N - 1)."""
+    D = lc_d_matrix(A, B, m_a)
+    dd, bd = np.diag(D), np.diag(B)
+    f = 1.0 / (2.0 * m_a) - (0.0 if np.isinf(M) else 1.0 / M)
+    return (np.outer(dd, dd) + D * D + f * f * (np.outer(bd, bd) + B * B)) / (n_mock - 1)
+
+
+def chi2_2(var_n2: np.ndarray, Cref: np.ndarray) -> float:
+    """<chi^2_2> of Sect. 5.3: the element variances at N = 2, normalised by the
+    reference diagonal, averaged over all P^2 elements."""
+    d = np.diag(Cref)
+    return float((var_n2 / np.outer(d, d)).sum() / Cref.shape[0] ** 2)
+
+
+def pair_cost_sample(M: float) -> float:
+    """Pair-count cost of one realisation of the sample covariance with the
+    split estimator, in units of the pairs of one data catalogue (Sect. 2.2):
+    DD (1) + DR with M N_d randoms (2M) + M split RR (M) = 1 + 3M."""
+    return 1.0 + 3.0 * M
+
+
+def pair_cost_lc(m_a: int) -> float:
+    """Pair-count cost of one realisation for LC (Sect. 2.3): DD (1), DR1 and
+    DR2 (2 x 2 M_a), RR1 and RR2 (2 x M_a^2); 7 for M_a = 1."""
+    return 1.0 + 4.0 * m_a + 2.0 * m_a * m_a
+
+
+def covcov_summary(A: np.ndarray, B: np.ndarray, m_a: int, M: float, Cref: Optional[np.ndarray] = None):
+    """<chi^2_2> of the LC and of the sample covariance at random ratio M (with
+    A, B standing in for their ensemble values and C = A + B/M for the
+    covariance), the pair-count costs, the inverse figures of merit
+    (cost x chi^2_2) and their ratio, the gain of LC (Sect. 5.3, Table 3)."""
+    C = A + B / M
+    ref = C if Cref is None else Cref
+    c_lc = chi2_2(lc_cov_element_var(A, B, m_a, M, 2), ref)
+    c_smp = chi2_2(sample_cov_element_var(C, 2), ref)
+    cost_lc, cost_smp = pair_cost_lc(m_a), pair_cost_sample(M)
+    return {"chi2_2_lc": c_lc, "chi2_2_smp": c_smp, "cost_lc": cost_lc, "cost_smp": cost_smp,
+            "ifom_lc": cost_lc * c_lc, "ifom_smp": cost_smp * c_smp,
+            "gain": (cost_smp * c_smp) / (cost_lc * c_lc)}
 
 
 # ---------------------------------------------------------------------------

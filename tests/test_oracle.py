@@ -6,6 +6,7 @@ follow from the estimator's definition, library routines (numpy covariance,
 Legendre quadrature) and the paper's analytic covariance for uniform data.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -388,3 +389,133 @@ def test_lc_matches_direct_large_random_covariance(oracle_mod):
     assert np.all((ratio > 0.6) & (ratio < 1.5)), ratio
     # the M = 2 covariance is measurably larger than the M = 6 one
     assert np.diag(Cb).mean() / direct.mean() > 1.3
+
+
+# ---------------------------------------------------------------------------
+# covariance of the covariance estimates (Sect. 3) and Table 3 (Sect. 5.3)
+# ---------------------------------------------------------------------------
+
+def _exchangeable(P, seed):
+    """Covariances S = Cov(x), T = Cov(x, x') of two exchangeable Gaussian
+    estimate vectors (a valid joint covariance [[S, T], [T, S]])."""
+    r = np.random.default_rng(seed)
+    G = r.normal(size=(2 * P, 2 * P))
+    J = G @ G.T + 0.5 * np.eye(2 * P)
+    S = 0.5 * (J[:P, :P] + J[P:, P:])
+    T = 0.5 * (J[:P, P:] + J[P:, :P])
+    return S, 0.5 * (T + T.T)
+
+
+@pytest.mark.parametrize("m_a,M", [(1, 50.0), (1, 2.0), (2, 7.0), (1, np.inf)])
+def test_lc_element_var_equals_term_by_term_expansion(oracle_mod, m_a, M):
+    """C^LC = a [c(x,x') + c(x',x)] + b [c(x,x) + c(x',x')] (Sect. 3.3) with
+    a = (1 - M_a/M)/2, b = M_a/(2M); expand Var(C^LC_ij) over the 16 products
+    with the Gaussian covariance of sample covariances, and compare with the
+    compact form (which needs D = A + B/(2 M_a))."""
+    P, N = 5, 40
+    S, T = _exchangeable(P, 3 + m_a)
+    A, B = T, m_a * (S - T)           # ensemble C^a = S, C^b = (S + T)/2
+    inv_m = 0.0 if np.isinf(M) else 1.0 / M
+    a, b = 0.5 * (1.0 - m_a * inv_m), 0.5 * m_a * inv_m
+
+    def E(p, q):
+        return S[p[1], q[1]] if p[0] == q[0] else T[p[1], q[1]]
+
+    def covc(u, v, w, z):             # Cov[c(u, v), c(w, z)] for Gaussian u, v, w, z
+        return (E(u, w) * E(v, z) + E(u, z) * E(v, w)) / (N - 1)
+
+    var = oracle_mod.lc_cov_element_var(A, B, m_a, M, N)
+    for i in range(P):
+        for j in range(P):
+            terms = [(a, (0, i), (1, j)), (a, (1, i), (0, j)), (b, (0, i), (0, j)), (b, (1, i), (1, j))]
+            exact = sum(c1 * c2 * covc(u1, v1, u2, v2) for c1, u1, v1 in terms for c2, u2, v2 in terms)
+            assert abs(var[i, j] - exact) <= 1e-12 * abs(exact)
+
+
+def test_covariance_element_vars_monte_carlo(oracle_mod):
+    """Gaussian x, x' with a known joint covariance, N = 12 realisations per
+    trial: the spread over 20000 trials of the sample covariance and of the LC
+    covariance built from c^a = (c(x) + c(x'))/2 and c^b = c((x + x')/2)
+    matches the predicted element variances (Sect. 3.2, 3.3)."""
+    P, N, trials, m_a, M = 3, 12, 20000, 1, 10.0
+    S, T = _exchangeable(P, 11)
+    J = np.block([[S, T], [T, S]])
+    L = np.linalg.cholesky(J)
+    r = np.random.default_rng(12)
+    z = r.normal(size=(trials, N, 2 * P)) @ L.T
+    x, xp = z[..., :P], z[..., P:]
+
+    def scov(v):
+        d = v - v.mean(axis=1, keepdims=True)
+        return np.einsum("tni,tnj->tij", d, d) / (N - 1)
+
+    ca = 0.5 * (scov(x) + scov(xp))
+    cb = scov(0.5 * (x + xp))
+    C = (2 * cb - ca) + 2 * m_a * (ca - cb) / M
+    var_lc = C.var(axis=0, ddof=1)
+    var_smp = scov(x).var(axis=0, ddof=1)
+    A, B = T, m_a * (S - T)
+    pred_lc = oracle_mod.lc_cov_element_var(A, B, m_a, M, N)
+    pred_smp = oracle_mod.sample_cov_element_var(S, N)
+    # the sample variance of 20000 draws is within about 3% of its mean
+    assert np.all(np.abs(var_lc / pred_lc - 1.0) < 0.06), var_lc / pred_lc
+    assert np.all(np.abs(var_smp / pred_smp - 1.0) < 0.06), var_smp / pred_smp
+
+
+def _golden(name):
+    rows = []
+    for line in open(os.path.join(os.path.dirname(__file__), "golden", name)):
+        if line.strip() and not line.startswith("#"):
+            rows.append(line.split())
+    return rows
+
+
+def test_poisson_mock_std_ratio_matches_paper(oracle_mod):
+    """Sect. 5.1: for random mocks at M = 50 the LC covariance's diagonal has
+    2.7 times the standard deviation of the sample covariance's.  Their
+    covariance is diagonal with C(M) ~ 1 + 3/M, i.e. A : B = 1 : 3."""
+    g = {k: float(v) for k, v in _golden("poisson_std_ratio.txt")}
+    M, m_a = g["M"], int(g["m_a"])
+    A, B = np.eye(4), 3.0 * np.eye(4)
+    ratio = np.sqrt(oracle_mod.lc_cov_element_var(A, B, m_a, M, 100)[0, 0]
+                    / oracle_mod.sample_cov_element_var(A + B / M, 100)[0, 0])
+    assert abs(ratio - g["ratio"]) < 0.05, ratio
+    # the printed definition D = A + B/M_a would give about 4.0
+    D_printed = A + B / m_a
+    f = 1.0 / (2 * m_a) - 1.0 / M
+    alt = np.sqrt((2 * D_printed[0, 0] ** 2 + f * f * 2 * B[0, 0] ** 2) / (2 * (A + B / M)[0, 0] ** 2))
+    assert abs(alt - g["ratio"]) > 1.0
+
+
+def _last_digit(txt):
+    return 10.0 ** -(len(txt.split(".")[1]) if "." in txt else 0)
+
+
+def test_table3_costs_and_figures_of_merit(oracle_mod):
+    """Table 3: the pair-count cost per realisation (1 + 3M for the sample
+    covariance, 7 for LC with M_a = 1), iFoM = cost x chi^2_2 and the ratio of
+    the two iFoMs.  The printed iFoMs and ratios were formed from unrounded
+    chi^2_2 and are themselves rounded (some LC values at M = 50 look
+    truncated), so each is allowed one unit of its last printed digit plus
+    the rounding of the printed chi^2_2."""
+    for row in _golden("table3_covcov.txt"):
+        M, dr, c_smp, c_lc, x_smp, x_lc, f_smp, f_lc, ratio = map(float, row)
+        assert oracle_mod.pair_cost_sample(M) == c_smp
+        assert oracle_mod.pair_cost_lc(1) == c_lc
+        i_smp, i_lc = c_smp * x_smp, c_lc * x_lc
+        assert abs(i_smp - f_smp) <= _last_digit(row[6]) + c_smp * 5e-4, row
+        assert abs(i_lc - f_lc) <= _last_digit(row[7]) + c_lc * 5e-4, row
+        assert abs(i_smp / i_lc - ratio) <= _last_digit(row[8]) + 0.01 * ratio, row
+
+
+def test_covcov_summary_consistency(oracle_mod):
+    """covcov_summary: chi^2_2 of the sample covariance equals the LC one when
+    M = 2 M_a (the two estimators coincide there, Sect. 3.3), and the gain is
+    the ratio of the iFoMs."""
+    S, T = _exchangeable(6, 21)
+    A, B = T, S - T
+    s2 = oracle_mod.covcov_summary(A, B, 1, 2.0)
+    assert abs(s2["chi2_2_lc"] - s2["chi2_2_smp"]) <= 1e-12 * s2["chi2_2_smp"]
+    s50 = oracle_mod.covcov_summary(A, B, 1, 50.0)
+    assert abs(s50["gain"] - s50["ifom_smp"] / s50["ifom_lc"]) < 1e-12 * s50["gain"]
+    assert s50["cost_smp"] == 151.0 and s50["cost_lc"] == 7.0
