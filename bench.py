@@ -212,6 +212,9 @@ def main():
                                          "per_mock_s": float(np.median(tp)),
                                          "speedup": float(np.median(tp) / np.median(ts))}
 
+    # predicted error of the covariance estimates at M = 50 (Sect. 3, 5.3)
+    out["covcov_M50"] = pl.covcov(50.0)
+
     if args.direct_mocks > 0 and not cats.wl.per_mock_randoms:
         # The cost the linear construction avoids (Sect. 2.3, Table 3): the
         # direct split estimate over all M random sub-catalogues needs DD and M

@@ -248,6 +248,38 @@ lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, int32_t n_ta
 lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32_t P, int32_t precision, double* C,
                                void* stream);
 
+/* Summary of lc_covcov (Sect. 5.3, Table 3). */
+typedef struct {
+    double chi2_2_lc, chi2_2_smp;   /* <chi^2_2> of the LC and of the sample covariance */
+    double cost_lc, cost_smp;       /* pair-count cost per realisation (units of the pairs of
+                                       one data catalogue): 1 + 4 M_a + 2 M_a^2 and 1 + 3M */
+    double ifom_lc, ifom_smp;       /* inverse figures of merit, cost x chi^2_2 */
+    double gain;                    /* ifom_smp / ifom_lc */
+} lc_covcov_report;
+
+/*
+ * lc_covcov: the error of the covariance estimates for Gaussian data vectors
+ * (covariance of covariance, Sect. 3.2 and 3.3), from A and B of lc_covariance
+ * standing in for their ensemble values:
+ *   sample covariance at ratio M:  Var C_ij = (C_ii C_jj + C_ij^2)/(N-1), C = A + B/M;
+ *   LC covariance at ratio M:      Var C_ij = (D_ii D_jj + D_ij^2
+ *                                   + (1/(2M_a) - 1/M)^2 (B_ii B_jj + B_ij^2))/(N-1),
+ *   with D = A + B/(2 M_a), the ensemble covariance at M = 2 M_a.  (The
+ *   paper prints D = A + B/M_a; only A + B/(2 M_a) reproduces the formula's
+ *   derivation from the two estimates.)
+ *   A, B     DEVICE double [P][P].
+ *   Cref     DEVICE double [P][P] normalising chi^2_2 (its diagonal), or NULL
+ *            for C = A + B/M.
+ *   n_mock   N for the standard deviations (>= 2 when sd_lc or sd_smp is given).
+ *   sd_lc, sd_smp  DEVICE double [P][P] or NULL: element standard deviations.
+ *   rep      HOST or NULL; non-NULL synchronises `stream`.  chi^2_2 averages
+ *            the N = 2 variances over all P^2 elements, each divided by
+ *            Cref_ii Cref_jj (Eq. chi2, Sect. 5.3).
+ * M = INFINITY is allowed (the sample covariance's cost is then infinite).
+ */
+lc_status lc_covcov(const double* A, const double* B, int32_t P, int32_t m_a, double M, const double* Cref,
+                    int32_t n_mock, double* sd_lc, double* sd_smp, lc_covcov_report* rep, void* stream);
+
 /* Result of lc_autotune: the mesh options and launch tuning to use. */
 typedef struct {
     int32_t cell_units;       /* for lc_mesh_opts.cell_units */

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ER
 
 # the exported symbols of include/lc.h
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
-           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance",
+           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance", "lc_covcov",
            "lc_autotune", "lc_release_caches"]
 
 
@@ -84,6 +84,15 @@ class lc_autotune_result(ctypes.Structure):
                 "cached": bool(self.cached)}
 
 
+class lc_covcov_report(ctypes.Structure):
+    _fields_ = [("chi2_2_lc", ctypes.c_double), ("chi2_2_smp", ctypes.c_double), ("cost_lc", ctypes.c_double),
+                ("cost_smp", ctypes.c_double), ("ifom_lc", ctypes.c_double), ("ifom_smp", ctypes.c_double),
+                ("gain", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class lc_cov_report(ctypes.Structure):
     _fields_ = [("chol_ok", ctypes.c_int32 * 2), ("n_neg_eig", ctypes.c_int32 * 2),
                 ("min_eig", ctypes.c_double * 2), ("max_eig", ctypes.c_double * 2),
@@ -128,6 +137,9 @@ def lib():
     L.lc_xi_split.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, i32, vp, vp]
     L.lc_sample_covariance.restype = st
     L.lc_sample_covariance.argtypes = [vp, i32, i32, i32, vp, vp]
+    L.lc_covcov.restype = st
+    L.lc_covcov.argtypes = [vp, vp, i32, i32, ctypes.c_double, vp, i32, vp, vp, ctypes.POINTER(lc_covcov_report),
+                            vp]
     L.lc_autotune.restype = st
     L.lc_autotune.argtypes = [vp, i64, vp, i32, ctypes.POINTER(lc_binning), vp, i32, i32, vp,
                               ctypes.POINTER(lc_autotune_result)]
@@ -292,6 +304,15 @@ def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, 
 def lc_sample_covariance(x, n_mock: int, P: int, precision: int, C, stream=None):
     _check(lib().lc_sample_covariance(_dptr(x), int(n_mock), int(P), int(precision), _dptr(C),
                                       _stream(stream)))
+
+
+def lc_covcov(A, B, P: int, m_a: int, M: float, Cref=None, n_mock: int = 0, sd_lc=None, sd_smp=None,
+              report: bool = True, stream=None) -> Optional[dict]:
+    rep = lc_covcov_report() if report else None
+    _check(lib().lc_covcov(_dptr(A), _dptr(B), int(P), int(m_a), float(M), _dptr(Cref), int(n_mock),
+                           _dptr(sd_lc), _dptr(sd_smp), ctypes.byref(rep) if rep is not None else None,
+                           _stream(stream)))
+    return rep.as_dict() if rep is not None else None
 
 
 def lc_autotune(xyz, cat_offsets, binning: Binning, tasks, sample_tasks: int = 0, stream=None) -> dict:

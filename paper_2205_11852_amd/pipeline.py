@@ -155,6 +155,21 @@ class Pipeline:
         self.xi_multipoles()
         return self.covariance(precision, report)
 
+    def covcov(self, M: Optional[float] = None, n_mock: int = 0, sd: bool = False) -> dict:
+        """Covariance-of-covariance summary (chi^2_2, cost, iFoM, gain) of the
+        last lc_covariance call's A and B at ratio M; with sd, also the element
+        standard deviations of both estimators at n_mock realisations."""
+        P = self.binning.P
+        sd_lc = sd_smp = None
+        if sd:
+            sd_lc = self.torch.empty((P, P), dtype=self.torch.float64, device=self.device)
+            sd_smp = self.torch.empty_like(sd_lc)
+        rep = lc.lc_covcov(self.A, self.B, P, self.m_a, self.M if M is None else M, None,
+                           n_mock or self.n_mock, sd_lc, sd_smp)
+        if sd:
+            rep["sd_lc"], rep["sd_smp"] = sd_lc, sd_smp
+        return rep
+
     def direct_estimates(self, mocks: Sequence[int], subsets: Sequence[int], tune: Optional[dict] = None):
         """The split estimate of each listed mock over all listed random
         sub-catalogues (M = len(subsets)): counts every needed task in one

@@ -164,3 +164,11 @@ def test_xi_split_and_sample_covariance_reject_bad_arguments(L):
     assert L.lc_sample_covariance(0x1000, 1, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_sample_covariance(0x1000, 5, 10, 7, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_sample_covariance(None, 5, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID
+
+
+def test_covcov_rejects_bad_arguments(L):
+    rep = lc.lc_covcov_report()
+    assert L.lc_covcov(None, 0x1000, 4, 1, 50.0, None, 10, None, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
+    assert L.lc_covcov(0x1000, 0x2000, 4, 0, 50.0, None, 10, None, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
+    assert L.lc_covcov(0x1000, 0x2000, 4, 1, -1.0, None, 10, None, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
+    assert L.lc_covcov(0x1000, 0x2000, 4, 1, 50.0, None, 1, 0x3000, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID

@@ -405,3 +405,34 @@ def test_split_estimate_with_two_subsets_matches_xi_multipoles(c1, torch, lcmod)
     a, b = x.cpu().numpy(), pl.xi[:, 2, :].cpu().numpy()
     assert np.array_equal(np.isnan(a), np.isnan(b))
     assert np.array_equal(a[np.isfinite(a)], b[np.isfinite(b)])
+
+
+@pytest.mark.parametrize("P,M,use_ref", [(37, 50.0, False), (2120, 50.0, False), (2120, 10.0, True),
+                                         (120, float("inf"), False)])
+def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref):
+    """Covariance of the covariance estimates and the Table 3 summary on the
+    device against the oracle (float64, 1e-12)."""
+    r = np.random.default_rng(P)
+    G = r.normal(size=(2 * P, 2 * P)) / np.sqrt(P)
+    J = G @ G.T + np.eye(2 * P)
+    S, T = 0.5 * (J[:P, :P] + J[P:, P:]), 0.5 * (J[:P, P:] + J[P:, :P])
+    A, B = 0.5 * (T + T.T), S - 0.5 * (T + T.T)
+    ref = (A + 2.0 * B) if use_ref else None
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dref = torch.from_numpy(ref).cuda() if use_ref else None
+    sd_lc = torch.empty((P, P), dtype=torch.float64, device="cuda")
+    sd_smp = torch.empty_like(sd_lc)
+    n = 500
+    rep = lcmod.lc_covcov(dA, dB, P, 1, M, dref, n, sd_lc, sd_smp)
+    exp = oracle_mod.covcov_summary(A, B, 1, M, ref) if np.isfinite(M) else None
+    if exp is not None:
+        for k in ("chi2_2_lc", "chi2_2_smp", "ifom_lc", "ifom_smp", "gain"):
+            assert abs(rep[k] - exp[k]) <= 1e-12 * abs(exp[k]), (k, rep[k], exp[k])
+        assert rep["cost_lc"] == exp["cost_lc"] and rep["cost_smp"] == exp["cost_smp"]
+    else:
+        exp_lc = oracle_mod.chi2_2(oracle_mod.lc_cov_element_var(A, B, 1, M, 2), A)
+        assert abs(rep["chi2_2_lc"] - exp_lc) <= 1e-12 * exp_lc
+    v_lc = oracle_mod.lc_cov_element_var(A, B, 1, M, n)
+    v_smp = oracle_mod.sample_cov_element_var(A + (0.0 if np.isinf(M) else 1.0 / M) * B, n)
+    assert np.allclose(sd_lc.cpu().numpy(), np.sqrt(v_lc), rtol=1e-12, atol=0)
+    assert np.allclose(sd_smp.cpu().numpy(), np.sqrt(v_smp), rtol=1e-12, atol=0)
