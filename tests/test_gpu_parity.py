@@ -413,10 +413,9 @@ def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref):
     """Covariance of the covariance estimates and the Table 3 summary on the
     device against the oracle (float64, 1e-12)."""
     r = np.random.default_rng(P)
-    G = r.normal(size=(2 * P, 2 * P)) / np.sqrt(P)
-    J = G @ G.T + np.eye(2 * P)
-    S, T = 0.5 * (J[:P, :P] + J[P:, P:]), 0.5 * (J[:P, P:] + J[P:, :P])
-    A, B = 0.5 * (T + T.T), S - 0.5 * (T + T.T)
+    G1, G2 = r.normal(size=(P, P)) / np.sqrt(P), r.normal(size=(P, P)) / np.sqrt(P)
+    A = G1 @ G1.T + 0.1 * np.eye(P)      # positive definite, like the covariances
+    B = 3.0 * (G2 @ G2.T)                # the random-catalogue part
     ref = (A + 2.0 * B) if use_ref else None
     dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
     dref = torch.from_numpy(ref).cuda() if use_ref else None
