@@ -368,73 +368,88 @@ __global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ W, in
         }
 }
 
-// Householder step k: v from row k (= column k of the symmetric trailing
-// matrix), tau, d[k], e[k].
-__global__ void k_hh_vec(const double* __restrict__ W, int64_t n, int64_t k, double* __restrict__ v,
-                         double* __restrict__ tau, double* __restrict__ d, double* __restrict__ e) {
-    __shared__ double red[256];
-    const int64_t m = n - k - 1;
-    const double* row = W + k * n + k + 1;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += row[i] * row[i];
-    red[threadIdx.x] = s;
+// Sum of x over the block (every thread gets the total).
+__device__ __forceinline__ double block_sum(double x, double* red) {
+    red[threadIdx.x] = x;
     __syncthreads();
     for (int o = blockDim.x / 2; o > 0; o >>= 1) {
         if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
         __syncthreads();
     }
-    const double norm2 = red[0];
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// Householder step k (tridiagonalisation of the symmetric trailing matrix),
+// part 1: every block forms the Householder vector of row k itself (a
+// reduction over m <= n values held in L2), then p = tau A22 v, one wave per
+// row, and the block's share of v.p; block 0 also stores v, tau, d[k], e[k].
+__global__ __launch_bounds__(256) void k_hh_step1(const double* __restrict__ W, int64_t n, int64_t k,
+                                                  double* __restrict__ v, double* __restrict__ tau,
+                                                  double* __restrict__ d, double* __restrict__ e,
+                                                  double* __restrict__ pv, double* __restrict__ vp_part) {
+    __shared__ double red[256];
+    __shared__ double wsum[4];
+    const int64_t m = n - k - 1;
+    const double* row = W + k * n + k + 1;
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += row[i] * row[i];
+    const double norm2 = block_sum(s, red);
     const double x0 = row[0];
     const double nrm = sqrt(norm2);
     const double alpha = x0 > 0 ? -nrm : nrm;   // reflect x onto alpha * e1
     const double v0 = x0 - alpha;
     const double vnorm2 = norm2 - x0 * x0 + v0 * v0;
     const bool trivial = !(vnorm2 > 0.0) || (norm2 - x0 * x0) <= 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v[i] = trivial ? 0.0 : (i == 0 ? v0 : row[i]);
-    if (threadIdx.x == 0) {
-        d[k] = W[k * n + k];
-        e[k] = trivial ? x0 : alpha;
-        *tau = trivial ? 0.0 : 2.0 / vnorm2;
+    const double t = trivial ? 0.0 : 2.0 / vnorm2;
+    if (blockIdx.x == 0) {
+        for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v[i] = trivial ? 0.0 : (i == 0 ? v0 : row[i]);
+        if (threadIdx.x == 0) {
+            d[k] = W[k * n + k];
+            e[k] = trivial ? x0 : alpha;
+            *tau = t;
+        }
     }
-}
-
-// p = tau * A22 v, one wave per row of the trailing matrix
-__global__ void k_hh_matvec(const double* __restrict__ W, int64_t n, int64_t k, const double* __restrict__ v,
-                            const double* __restrict__ tau, double* __restrict__ pv) {
-    const int64_t m = n - k - 1;
-    const int lane = threadIdx.x & 63;
-    const int64_t r = (blockIdx.x * int64_t(blockDim.x) + threadIdx.x) >> 6;
-    if (r >= m) return;
-    const double* row = W + (k + 1 + r) * n + k + 1;
-    double s = 0.0;
-    for (int64_t j = lane; j < m; j += 64) s += row[j] * v[j];
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) pv[r] = *tau * s;
-}
-
-// w = p - (tau/2)(v.p) v
-__global__ void k_hh_w(int64_t m, const double* __restrict__ v, const double* __restrict__ tau,
-                       const double* __restrict__ pv, double* __restrict__ w) {
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += v[i] * pv[i];
-    red[threadIdx.x] = s;
+    // p_r = tau sum_j A22[r][j] v_j (v_j from row k, v_0 = x0 - alpha)
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = blockIdx.x * int64_t(blockDim.x >> 6) + wv;
+    double vpr = 0.0;
+    if (r < m) {
+        const double* ar = W + (k + 1 + r) * n + k + 1;
+        double acc = 0.0;
+        for (int64_t j = lane; j < m; j += 64) acc += ar[j] * (j == 0 ? v0 : row[j]);
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+        const double p = trivial ? 0.0 : t * acc;
+        if (lane == 0) pv[r] = p;
+        vpr = trivial ? 0.0 : p * (r == 0 ? v0 : row[r]);
+    }
+    if (lane == 0) wsum[wv] = vpr;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0;
+        for (int q = 0; q < int(blockDim.x >> 6); q++) b += wsum[q];
+        vp_part[blockIdx.x] = b;
     }
-    const double K = 0.5 * *tau * red[0];
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) w[i] = pv[i] - K * v[i];
 }
 
-// A22 -= v w^T + w v^T
-__global__ void k_hh_update(double* __restrict__ W, int64_t n, int64_t k, const double* __restrict__ v,
-                            const double* __restrict__ w) {
+// Householder step k, part 2: every block forms K = (tau/2)(v.p) from the
+// n1 partial sums (in a fixed order) and applies A22 -= v w^T + w v^T with
+// w = p - K v to its part of A22.
+__global__ __launch_bounds__(256) void k_hh_step2(double* __restrict__ W, int64_t n, int64_t k,
+                                                  const double* __restrict__ v, const double* __restrict__ tau,
+                                                  const double* __restrict__ pv, const double* __restrict__ vp_part,
+                                                  int64_t n1) {
+    __shared__ double red[256];
     const int64_t m = n - k - 1;
-    for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < m * m; t += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t i = t / m, j = t % m;
-        W[(k + 1 + i) * n + k + 1 + j] -= v[i] * w[j] + w[i] * v[j];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n1; i += blockDim.x) s += vp_part[i];
+    const double K = 0.5 * *tau * block_sum(s, red);
+    for (int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; q < m * m;
+         q += int64_t(gridDim.x) * blockDim.x) {
+        const int64_t i = q / m, j = q % m;
+        const double wi = pv[i] - K * v[i], wj = pv[j] - K * v[j];
+        W[(k + 1 + i) * n + k + 1 + j] -= v[i] * wj + wi * v[j];
     }
 }
 
@@ -531,17 +546,17 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     double* aux = nullptr;
     CheckFlags* fl = nullptr;
     LC_TRY(dev_alloc((void**)&W, sizeof(double) * n * n, s));
-    const int64_t naux = 5 * n + 16;
+    const int64_t naux = 6 * n + 16;
     LC_TRY(dev_alloc((void**)&aux, sizeof(double) * naux, s));
     LC_TRY(dev_alloc((void**)&fl, sizeof(CheckFlags) * 2, s));
     k_zero_flags<<<1, 64, 0, s>>>(fl, 2);
     double* v = aux;
     double* pv = aux + n;
-    double* w = aux + 2 * n;
     double* d = aux + 3 * n;
     double* e = aux + 4 * n;
     double* tau = aux + 5 * n;
     double* res = aux + 5 * n + 4;
+    double* vpp = aux + 5 * n + 16;     // partial sums of v.p, (n + 3)/4 of them
     // Cholesky
     k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl);
     for (int64_t k0 = 0; k0 < n; k0 += kNB) {
@@ -558,10 +573,10 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl + 1);
     for (int64_t k = 0; k + 2 < n; k++) {
         const int64_t m = n - k - 1;
-        k_hh_vec<<<1, 256, 0, s>>>(W, n, k, v, tau, d, e);
-        k_hh_matvec<<<nblocks(m * 64, 256, 1 << 20), 256, 0, s>>>(W, n, k, v, tau, pv);
-        k_hh_w<<<1, 256, 0, s>>>(m, v, tau, pv, w);
-        k_hh_update<<<nblocks(m * m, 256), 256, 0, s>>>(W, n, k, v, w);
+        // one wave per row of p (4 per block)
+        const int64_t n1 = (m + 3) / 4;
+        k_hh_step1<<<unsigned(n1), 256, 0, s>>>(W, n, k, v, tau, d, e, pv, vpp);
+        k_hh_step2<<<nblocks(m * m, 256, 1024), 256, 0, s>>>(W, n, k, v, tau, pv, vpp, n1);
     }
     k_hh_tail<<<1, 64, 0, s>>>(W, n, d, e);
     k_bisect<<<1, 256, 0, s>>>(d, e, n, fl + 1, res);
