@@ -44,7 +44,7 @@ typedef int32_t lc_status;
 #define LC_LOS_Z    0       /* plane-parallel, line of sight = z axis (Sect. 4.1) */
 #define LC_LOS_MID  1       /* line of sight = pair midpoint seen from the origin (open geometry) */
 
-#define LC_MAX_BINS 8192    /* n_r * n_mu */
+#define LC_MAX_BINS 32768   /* n_r * n_mu (the block histogram lives in LDS) */
 #define LC_MAX_NMU  1024
 
 /* Thread-local message of the last failed call; valid until the next lc_* call. */
@@ -135,7 +135,9 @@ typedef struct { int32_t cat_a, cat_b; } lc_task;
 /* Tuning knobs; NULL or 0 fields = library defaults. */
 typedef struct {
     int32_t cells_per_item;   /* cells of one catalogue per work item */
-    int32_t waves_per_block;  /* 1, 2, 4, 8 (default 4): waves sharing a work item and a histogram */
+    int32_t waves_per_block;  /* 1, 2, 4, 8, 16 (default: the shape with the most resident waves per CU,
+                                 4 unless a large histogram leaves LDS for one block only): waves sharing
+                                 a work item and a histogram */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
     int32_t chunk;            /* i points tested together against each gathered j set:
                                  a multiple of 4 in [4, 256] ([4, 64] for LC_LOS_MID);
@@ -224,8 +226,11 @@ lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n
  *   counts, tasks, cat_sizes  as for lc_xi_multipoles.
  *   est     HOST int32 [n_mock][1 + 2 n_sub]: task ids of DD, DR_1 .. DR_M,
  *           RR_1 .. RR_M; DD = (D,D), DR_i = (D,R_i), RR_i = (R_i,R_i), R_i != D.
- *   xi      DEVICE double [n_mock][P], P = n_r*n_mu + 3*n_r, written (layout as
- *           one estimate of lc_xi_multipoles).
+ *   xi      DEVICE double, row n (P = n_r*n_mu + 3*n_r values, laid out as one
+ *           estimate of lc_xi_multipoles) at xi + n * ld_xi, written.
+ *   ld_xi   row stride in doubles, >= P; 0 means P.  ld_xi = 3P with xi
+ *           offset by e*P writes estimate e of the [n_mock][3][P] layout
+ *           that lc_covariance and lc_covariance_general read.
  * Same normalisation and estimator as lc_xi_multipoles, the sums over
  * subsets taken in the order given; with n_sub = 2 it reproduces that call's
  * third estimate.  Errors: LC_ERR_INVALID for inconsistent task ids or
@@ -233,7 +238,71 @@ lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n
  */
 lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, int32_t n_tasks,
                       const int64_t* cat_sizes, int32_t n_cat, const int32_t* est, int32_t n_sub,
-                      int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, void* stream);
+                      int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, int64_t ld_xi, void* stream);
+
+/*
+ * lc_covariance_general: the construction from covariances at two general
+ * random/data ratios M_a < M_b (Sect. 2.3, Eq. CovAB):
+ *   A = (M_b C^b - M_a C^a)/(M_b - M_a),  B = M_a M_b (C^a - C^b)/(M_b - M_a),
+ *   C = A + B/M  (M = INFINITY gives A),
+ * with C^a = (Cov x + Cov x')/2 and C^b = Cov y over the mocks.
+ *   xi        DEVICE double [n_mock][3][P]: per mock two estimates x, x' with
+ *             ratio M_a and one estimate y with ratio M_b (lc_xi_split with
+ *             ld_xi = 3P fills it); any data vector, e.g. after lc_map_vectors.
+ *   n_split   the check treats [0, n_split) and [n_split, P) as two blocks
+ *             (0 <= n_split <= P; an empty block reports chol_ok = 1,
+ *             n_neg_eig = 0 and NaN extremes).
+ *   m_a, m_b  0 < m_a < m_b < infinity.
+ *   precision, A, B, C, rep as for lc_covariance, which is this call with
+ *             P = n_r*n_mu + 3*n_r, n_split = n_r*n_mu and M_b = 2 M_a.
+ * Errors: LC_ERR_INVALID for NULL xi or C, n_mock < 2, P or n_split out of
+ * range, bad ratios or precision.  Asynchronous unless rep is given.
+ */
+lc_status lc_covariance_general(const double* xi, int32_t n_mock, int32_t P, int32_t n_split, double m_a,
+                                double m_b, double M, int32_t precision, double* A, double* B, double* C,
+                                lc_cov_report* rep, void* stream);
+
+/*
+ * lc_rebin_counts: co-added pair counts (Sect. 4.3: the one-dimensional
+ * correlation function co-adds the counts over mu; wider r bins co-add
+ * adjacent r bins).  Exact uint64 sums.
+ *   counts  DEVICE uint64 [n_tasks][n_r][n_mu], read.
+ *   w_r     r bins per output bin, 1 <= w_r <= n_r; the last output bin takes
+ *           the n_r mod w_r bins that are left (edges e_0, e_{w_r}, ..., e_{n_r}).
+ *   w_mu    mu bins per output bin; must divide n_mu (the output mu bins stay
+ *           uniform; w_mu = n_mu gives one bin, the 1D count).
+ *   out     DEVICE uint64 [n_tasks][ceil(n_r/w_r)][n_mu/w_mu], written; must
+ *           not alias counts.  It feeds lc_xi_multipoles / lc_xi_split with
+ *           the output n_r and n_mu.
+ * Errors: LC_ERR_INVALID for bad sizes or NULL buffers.  Asynchronous.
+ */
+lc_status lc_rebin_counts(const uint64_t* counts, int32_t n_tasks, int32_t n_r, int32_t n_mu, int32_t w_r,
+                          int32_t w_mu, uint64_t* out, void* stream);
+
+/*
+ * lc_map_vectors / lc_map_matrix: a linear map T of data vectors in which
+ * input element i goes, with weight weight[i], to output element group[i]
+ * (group[i] = -1 drops it).  Re-binning (weights 1/w over w adjacent bins)
+ * and selecting (e.g. the multipoles over a range of r) are such maps; the
+ * construction is linear, so it commutes with them (Sect. 2.3), and the
+ * covariances can be re-binned after the fact (Sect. 5.3).
+ *   group, weight  HOST [P_in], read before the call returns; every group
+ *                  id in [-1, P_out), weights finite.
+ *   lc_map_vectors: y_n = T x_n for n_vec rows; x DEVICE double, row n at
+ *                  x + n ld_x; y DEVICE double, row n at y + n ld_y, written
+ *                  (ld 0 = dense).  Each output sums w_i x_i over its members
+ *                  in increasing i.  The [n_mock][3][P] layout maps as
+ *                  n_vec = 3 n_mock rows.
+ *   lc_map_matrix: Y = T X T^T; X DEVICE double [P_in][P_in], Y DEVICE double
+ *                  [P_out][P_out], written.  Y_gh = sum_a w_a (sum_b w_b X_ab)
+ *                  over a in g, b in h, increasing.
+ * Outputs with no member are 0.  y / Y must not alias the input.  Errors:
+ * LC_ERR_INVALID for bad sizes, ids, weights or NULL buffers.  Asynchronous.
+ */
+lc_status lc_map_vectors(const double* x, int64_t n_vec, int32_t P_in, int64_t ld_x, const int32_t* group,
+                         const double* weight, int32_t P_out, double* y, int64_t ld_y, void* stream);
+lc_status lc_map_matrix(const double* X, int32_t P_in, const int32_t* group, const double* weight, int32_t P_out,
+                        double* Y, void* stream);
 
 /*
  * lc_sample_covariance: the sample covariance over mocks of one estimate
@@ -294,12 +363,13 @@ typedef struct {
 
 /*
  * lc_autotune: choose the mesh (cell side, sub-cell split) and the launch
- * shape (i points per gather) for a batch of tasks by timing them.
+ * shape (i points per gather, waves per block) for a batch of tasks by
+ * timing them.
  * Pair counts do not depend on these choices (they are exact); only the time
  * does, through the number of candidate tests and the cost of gathering
  * neighbour cells.  Candidates: cell sides r_max / k (k = 1, 1.5, 2, 3, 4) and
  * the default, each with sub-cell splits 1, 2 and 4; then chunks of i points
- * for the best mesh.  Each is timed with HIP events over `sample_tasks` tasks
+ * for the best mesh, then 4, 8 and 16 waves per block.  Each is timed with HIP events over `sample_tasks` tasks
  * spread evenly over the list (one untimed launch, then two timed).
  *   xyz, n_total, cat_offsets, n_cat, b   as for lc_build_cells.
  *   tasks     HOST [n_tasks], as for lc_pair_count_batch.

@@ -23,7 +23,11 @@ Everything below is the plain definition from the paper, in float64:
 * the covariance of the covariance estimates for Gaussian data vectors
   (Sect. 3.2, 3.3): element variances of the sample and of the LC
   covariance, and their summaries chi^2_2, pair-count cost and inverse
-  figure of merit (Sect. 5.3, Table 3).
+  figure of merit (Sect. 5.3, Table 3);
+* co-added (re-binned) pair counts, including the 1D count over all mu
+  (Sect. 4.3); linear maps of data vectors and covariances (re-binning,
+  selection; Sect. 2.3, 5.3); the construction from general M_a < M_b
+  (Eq. CovAB).
 
 Readings where the paper is silent (documented with the tests):
   mu is |mu| on [0, 1] with uniform bins, the last one closed at mu = 1;
@@ -287,6 +291,74 @@ def covcov_summary(A: np.ndarray, B: np.ndarray, m_a: int, M: float, Cref: Optio
     return {"chi2_2_lc": c_lc, "chi2_2_smp": c_smp, "cost_lc": cost_lc, "cost_smp": cost_smp,
             "ifom_lc": cost_lc * c_lc, "ifom_smp": cost_smp * c_smp,
             "gain": (cost_smp * c_smp) / (cost_lc * c_lc)}
+
+
+# ---------------------------------------------------------------------------
+# re-binning, the 1D correlation function and general M_a, M_b
+# (Sect. 2.3 Eq. CovAB, Sect. 4.3, Sect. 5.3)
+# ---------------------------------------------------------------------------
+
+def rebin_counts(counts: np.ndarray, w_r: int, w_mu: int) -> np.ndarray:
+    """Co-add pair counts [n_r, n_mu] over groups of w_r adjacent r bins (the
+    last group keeps what is left) and w_mu adjacent mu bins (w_mu divides
+    n_mu).  With w_mu = n_mu this is the 1D pair count of Sect. 4.3 (counts
+    co-added over mu).  Plain loops, uint64."""
+    n_r, n_mu = counts.shape
+    assert n_mu % w_mu == 0
+    n_r2 = (n_r + w_r - 1) // w_r
+    out = np.zeros((n_r2, n_mu // w_mu), dtype=np.uint64)
+    for k in range(n_r):
+        for m in range(n_mu):
+            out[k // w_r, m // w_mu] += np.uint64(counts[k, m])
+    return out
+
+
+def rebinned_edges(edges: Sequence[int], w_r: int) -> List[int]:
+    """Edges of the co-added r bins: every w_r-th edge and the last one."""
+    e = list(edges)
+    n_r = len(e) - 1
+    return [e[min(k * w_r, n_r)] for k in range((n_r + w_r - 1) // w_r + 1)]
+
+
+def linear_map(group: np.ndarray, weight: np.ndarray, P_out: int) -> np.ndarray:
+    """The dense matrix T [P_out, P_in] of a map that sends input element i
+    with weight w_i to output element group_i (group_i = -1: dropped)."""
+    T = np.zeros((P_out, len(group)))
+    for i, (g, w) in enumerate(zip(group, weight)):
+        if g >= 0:
+            T[g, i] += w
+    return T
+
+
+def map_vectors(X: np.ndarray, group, weight, P_out: int) -> np.ndarray:
+    """Rows of X [..., P_in] mapped by T: y = T x (re-binning or selecting the
+    elements of a data vector; any linear function of xi, Sect. 2.3)."""
+    return X @ linear_map(group, weight, P_out).T
+
+
+def map_matrix(C: np.ndarray, group, weight, P_out: int) -> np.ndarray:
+    """T C T^T: a covariance re-binned with the data vector (Sect. 5.3)."""
+    T = linear_map(group, weight, P_out)
+    return T @ C @ T.T
+
+
+def linear_construction_general(Ca: np.ndarray, Cb: np.ndarray, m_a: float, m_b: float, M: float):
+    """Eq. CovAB: from covariances at random ratios M_a < M_b,
+    A = (M_b C^b - M_a C^a) / (M_b - M_a), B = M_a M_b (C^a - C^b) / (M_b - M_a),
+    and C = A + B / M (M = inf -> A)."""
+    A = (m_b * Cb - m_a * Ca) / (m_b - m_a)
+    B = (m_a * m_b) * (Ca - Cb) / (m_b - m_a)
+    C = A.copy() if np.isinf(M) else A + B / M
+    return A, B, C
+
+
+def lc_from_vectors_general(V: np.ndarray, m_a: float, m_b: float, M: float):
+    """V [N, 3, P]: two estimates at ratio M_a and one at M_b per mock ->
+    (A, B, C, Ca, Cb) with C^a the mean of the two M_a covariances."""
+    Ca = 0.5 * (sample_cov(V[:, 0]) + sample_cov(V[:, 1]))
+    Cb = sample_cov(V[:, 2])
+    A, B, C = linear_construction_general(Ca, Cb, m_a, m_b, M)
+    return A, B, C, Ca, Cb
 
 
 # ---------------------------------------------------------------------------

@@ -17,7 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblc.so")
 ARCH = "gfx950"
-SOURCES = ["runtime.hip", "cells.hip", "paircount.hip", "xi.hip", "cov.hip", "covcov.hip", "autotune.hip"]
+SOURCES = ["runtime.hip", "cells.hip", "paircount.hip", "xi.hip", "cov.hip", "covcov.hip", "autotune.hip",
+           "rebin.hip"]
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -3,8 +3,10 @@
 //
 //   mean (float64, two passes)  ->  deviations  ->  Cov_e = D_e^T D_e / (N-1)
 //   for the three estimates e = (D,R1), (D,R2), (D,R1uR2)
-//   ->  C^a = (Cov_0 + Cov_1)/2, C^b = Cov_2, A = 2C^b - C^a,
-//       B = 2 M_a (C^a - C^b), C = A + B/M            (float64)
+//   ->  C^a = (Cov_0 + Cov_1)/2, C^b = Cov_2,
+//       A = (M_b C^b - M_a C^a)/(M_b - M_a), B = M_a M_b (C^a - C^b)/(M_b - M_a)
+//       (Eq. CovAB; 2C^b - C^a and 2 M_a (C^a - C^b) at M_b = 2 M_a),
+//       C = A + B/M                                    (float64)
 //   ->  Cholesky and eigenvalue extremes of each block of C (float64).
 //
 // The products D^T D run either in float64 (VALU) or as float32 MFMA
@@ -216,15 +218,19 @@ __global__ __launch_bounds__(256) void k_syrk32(const float* __restrict__ dev, i
 // ---------------------------------------------------------------------------
 // linear construction (float64)
 // ---------------------------------------------------------------------------
-__global__ void k_combine(const double* __restrict__ cov, int64_t PP, double two_ma, double M, int m_inf,
+__global__ void k_combine(const double* __restrict__ cov, int64_t PP, double m_a, double m_b, double M, int m_inf,
                           double* __restrict__ A, double* __restrict__ B, double* __restrict__ C) {
 #pragma clang fp contract(off)
+    // Eq. CovAB: A = (M_b C^b - M_a C^a)/(M_b - M_a), B = M_a M_b/(M_b - M_a) (C^a - C^b);
+    // at M_b = 2 M_a these are 2 C^b - C^a and 2 M_a (C^a - C^b), bit for bit
+    const double dm = m_b - m_a;
+    const double kb = (m_a * m_b) / dm;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < PP;
          t += int64_t(gridDim.x) * blockDim.x) {
         const double ca = 0.5 * (cov[t] + cov[PP + t]);
         const double cb = cov[2 * PP + t];
-        const double a = 2.0 * cb - ca;
-        const double b = two_ma * (ca - cb);
+        const double a = (m_b * cb - m_a * ca) / dm;
+        const double b = kb * (ca - cb);
         A[t] = a;
         B[t] = b;
         C[t] = m_inf ? a : a + b / M;
@@ -542,6 +548,12 @@ static int nblocks(int64_t n, int threads, int cap = 4096) {
 // Check one diagonal block [off, off+n) of C.  Writes chol_ok, n_neg, min, max.
 static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n, hipStream_t s,
                              int32_t* chol_ok, int32_t* n_neg, double* mn, double* mx) {
+    if (n == 0) {  // an empty block: nothing to factor, no eigenvalues
+        *chol_ok = 1;
+        *n_neg = 0;
+        *mn = *mx = NAN;
+        return LC_OK;
+    }
     double* W = nullptr;
     double* aux = nullptr;
     CheckFlags* fl = nullptr;
@@ -595,33 +607,23 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     return LC_OK;
 }
 
-}  // namespace lc
-
-using namespace lc;
-
-extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n_mu, int32_t m_a,
-                                   double M, int32_t precision, double* A, double* B, double* C,
-                                   lc_cov_report* rep, void* stream) {
-    clear_error();
-    if (!xi || !C) return fail(LC_ERR_INVALID, "xi and C must not be NULL");
-    if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
-    if (n_r < 1 || n_mu < 1 || n_mu > LC_MAX_NMU || int64_t(n_r) * n_mu > LC_MAX_BINS)
-        return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
-    if (m_a < 1) return fail(LC_ERR_INVALID, "m_a = %d, must be >= 1", m_a);
+// The sample covariances of the three estimates, the construction and the
+// check; blocks [0, split) and [split, P) of C are checked separately.
+static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, int64_t split, double m_a, double m_b,
+                                 double M, int32_t precision, double* A, double* B, double* C, lc_cov_report* rep,
+                                 hipStream_t s) {
     if (!(M > 0.0)) return fail(LC_ERR_INVALID, "M must be > 0 (or INFINITY)");
     if (precision != LC_FP64 && precision != LC_FP32_MFMA && precision != LC_FP32_MFMA_CHECKED)
         return fail(LC_ERR_INVALID, "precision = %d is not LC_FP64 / LC_FP32_MFMA / LC_FP32_MFMA_CHECKED",
                     precision);
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
-    hipStream_t s = (hipStream_t)stream;
+    (void)ctx;
     const int64_t N = n_mock;
-    const int64_t P = int64_t(n_r) * n_mu + 3 * int64_t(n_r);
     const int64_t PP = P * P;
     const int64_t W3 = 3 * P;
     const double denom = double(N - 1);
     const int m_inf = std::isinf(M) ? 1 : 0;
-
     double* mean = nullptr;
     double* part = nullptr;
     double* cov = nullptr;
@@ -658,13 +660,12 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
         dev_free(dev, s);
         return LC_OK;
     };
-    const double two_ma = 2.0 * double(m_a);
     if (precision == LC_FP64) {
         LC_TRY(run_fp64(cov));
     } else {
         LC_TRY(run_fp32(cov));
     }
-    k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, two_ma, M, m_inf, Aw, Bw, C);
+    k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, m_a, m_b, M, m_inf, Aw, Bw, C);
     double rel[3] = {-1.0, -1.0, -1.0};
     if (precision == LC_FP32_MFMA_CHECKED) {
         double *A64 = nullptr, *B64 = nullptr, *C64 = nullptr, *fpart = nullptr;
@@ -674,7 +675,7 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
         const int nfb = 512;
         LC_TRY(dev_alloc((void**)&fpart, sizeof(double) * 2 * nfb * 3, s));
         LC_TRY(run_fp64(cov));
-        k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, two_ma, M, m_inf, A64, B64, C64);
+        k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, m_a, m_b, M, m_inf, A64, B64, C64);
         k_frob<<<nfb, 256, 0, s>>>(C, C64, PP, fpart);
         k_frob<<<nfb, 256, 0, s>>>(Aw, A64, PP, fpart + 2 * nfb);
         k_frob<<<nfb, 256, 0, s>>>(Bw, B64, PP, fpart + 4 * nfb);
@@ -703,15 +704,46 @@ extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r
         rep->rel_frob_vs_fp64[0] = rel[0];
         rep->rel_frob_vs_fp64[1] = rel[1];
         rep->rel_frob_vs_fp64[2] = rel[2];
-        const int64_t nb0 = int64_t(n_r) * n_mu;
-        LC_TRY(check_block(C, P, 0, nb0, s, &rep->chol_ok[0], &rep->n_neg_eig[0], &rep->min_eig[0],
+        LC_TRY(check_block(C, P, 0, split, s, &rep->chol_ok[0], &rep->n_neg_eig[0], &rep->min_eig[0],
                            &rep->max_eig[0]));
-        LC_TRY(check_block(C, P, nb0, 3 * int64_t(n_r), s, &rep->chol_ok[1], &rep->n_neg_eig[1],
-                           &rep->min_eig[1], &rep->max_eig[1]));
+        LC_TRY(check_block(C, P, split, P - split, s, &rep->chol_ok[1], &rep->n_neg_eig[1], &rep->min_eig[1],
+                           &rep->max_eig[1]));
     }
     if (!A) dev_free(Aw, s);
     if (!B) dev_free(Bw, s);
     return LC_OK;
+}
+
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" lc_status lc_covariance(const double* xi, int32_t n_mock, int32_t n_r, int32_t n_mu, int32_t m_a,
+                                   double M, int32_t precision, double* A, double* B, double* C,
+                                   lc_cov_report* rep, void* stream) {
+    clear_error();
+    if (!xi || !C) return fail(LC_ERR_INVALID, "xi and C must not be NULL");
+    if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
+    if (n_r < 1 || n_mu < 1 || n_mu > LC_MAX_NMU || int64_t(n_r) * n_mu > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
+    if (m_a < 1) return fail(LC_ERR_INVALID, "m_a = %d, must be >= 1", m_a);
+    const int64_t nb0 = int64_t(n_r) * n_mu;
+    return covariance_impl(xi, n_mock, nb0 + 3 * int64_t(n_r), nb0, double(m_a), 2.0 * double(m_a), M, precision, A,
+                           B, C, rep, (hipStream_t)stream);
+}
+
+extern "C" lc_status lc_covariance_general(const double* xi, int32_t n_mock, int32_t P, int32_t n_split, double m_a,
+                                           double m_b, double M, int32_t precision, double* A, double* B, double* C,
+                                           lc_cov_report* rep, void* stream) {
+    clear_error();
+    if (!xi || !C) return fail(LC_ERR_INVALID, "xi and C must not be NULL");
+    if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
+    if (P < 1 || P > 4 * LC_MAX_BINS) return fail(LC_ERR_INVALID, "P = %d out of range", P);
+    if (n_split < 0 || n_split > P) return fail(LC_ERR_INVALID, "n_split = %d outside [0, P = %d]", n_split, P);
+    if (!(m_a > 0.0) || !(m_b > m_a) || !std::isfinite(m_b))
+        return fail(LC_ERR_INVALID, "need 0 < m_a < m_b < infinity (got %g, %g)", m_a, m_b);
+    return covariance_impl(xi, n_mock, P, n_split, m_a, m_b, M, precision, A, B, C, rep, (hipStream_t)stream);
 }
 
 extern "C" lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32_t P, int32_t precision, double* C,

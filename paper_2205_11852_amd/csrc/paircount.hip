@@ -469,7 +469,7 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
 // Six waves per SIMD (80 VGPRs): latency hiding pays more than the few
 // registers this spills outside the inner loops.
 template <int LOS, bool UNIFORM, bool HAS_EMIN>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
     const float* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
     const int32_t* __restrict__ order, const int4* __restrict__ sten, const ExactTab* __restrict__ xt,
     const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
@@ -858,23 +858,48 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     pl.mode = mode;
     pl.n_tasks = n_tasks;
 
-    int wpb = tune && tune->waves_per_block > 0 ? tune->waves_per_block : 4;
-    if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8)
-        return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4 or 8", wpb);
-    while (wpb > 1 && size_t(p.queue_byte0) + size_t(wpb) * (kQ + kX) * 16 > ctx->max_lds_block) wpb >>= 1;
-    pl.threads = wpb * 64;
-    pl.lds = size_t(p.queue_byte0) + size_t(wpb) * (kQ + kX) * 16;
-    // each wave's share of the 2^32 bound on a histogram bin
-    p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
-    if (pl.lds > ctx->max_lds_block)
+    auto lds_for = [&](int w) { return size_t(p.queue_byte0) + size_t(w) * (kQ + kX) * 16; };
+    if (lds_for(1) > ctx->max_lds_block)
         return fail(LC_ERR_INVALID, "histogram of %d bins does not fit in LDS", p.nbins);
-    if (pl.lds > 65536) {
+    if (lds_for(16) > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)pl.kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(pl.lds));
+                                           int(std::min(lds_for(16), ctx->max_lds_block)));
         if (e != hipSuccess) return fail(LC_ERR_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
     }
-    int occ = 0;
-    LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, pl.threads, pl.lds));
+    int wpb = 0, occ = 0;
+    if (tune && tune->waves_per_block > 0) {
+        wpb = tune->waves_per_block;
+        if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16)
+            return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4, 8 or 16", wpb);
+        while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
+        LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
+    } else {
+        // the block shape that keeps the most waves resident per CU, the
+        // smallest on a tie: a small histogram leaves room for several
+        // 4-wave blocks, a large one for a single block, which then holds
+        // more waves sharing its histogram
+        int best = -1;
+        for (int w : {4, 8, 16}) {
+            if (lds_for(w) > ctx->max_lds_block) continue;
+            int o = 0;
+            LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void*)pl.kern, w * 64, lds_for(w)));
+            if (o * w > best) {
+                best = o * w;
+                wpb = w;
+                occ = o;
+            }
+        }
+        if (wpb == 0) {
+            wpb = 4;
+            while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
+            LC_TRY_HIP(
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
+        }
+    }
+    pl.threads = wpb * 64;
+    pl.lds = lds_for(wpb);
+    // each wave's share of the 2^32 bound on a histogram bin
+    p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
     occ = std::max(occ, 1);
     int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, occ) : occ;
     pl.blocks = ctx->n_cu * bpc;

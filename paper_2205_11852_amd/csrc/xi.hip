@@ -61,11 +61,11 @@ __global__ void k_xi(const unsigned long long* __restrict__ counts, const int32_
 // One split estimate per mock with M random sub-catalogues (the sample
 // covariance's estimator, Sect. 2.1-2.2): est row = [DD, DR_1..DR_M,
 // RR_1..RR_M], norm row alike.  xi = (dd - (2/M) sum dr_i) / ((1/M) sum rr_i) + 1,
-// the sums taken in subset order.  Output [n_mock][P] (xi(r, mu) then the
-// multipoles).
+// the sums taken in subset order.  Output row n at xi + n ld (xi(r, mu) then
+// the multipoles, P values).
 __global__ void k_xi_split(const unsigned long long* __restrict__ counts, const int32_t* __restrict__ est,
                            const double* __restrict__ norm, const double* __restrict__ W, int32_t n_mock,
-                           int32_t n_sub, int32_t n_r, int32_t n_mu, double* __restrict__ xi) {
+                           int32_t n_sub, int32_t n_r, int32_t n_mu, int64_t ld, double* __restrict__ xi) {
 #pragma clang fp contract(off)
     const int64_t idx = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
     if (idx >= int64_t(n_mock) * n_r) return;
@@ -76,7 +76,7 @@ __global__ void k_xi_split(const unsigned long long* __restrict__ counts, const 
     const int32_t* e = est + w * mk;
     const double* nr = norm + w * mk;
     const double two_over_m = 2.0 / double(n_sub), one_over_m = 1.0 / double(n_sub);
-    double* out = xi + int64_t(mk) * P;
+    double* out = xi + int64_t(mk) * ld;
     double mp[3] = {0, 0, 0};
     const double nan = __builtin_nan("");
     for (int m = 0; m < n_mu; m++) {
@@ -183,11 +183,15 @@ extern "C" lc_status lc_xi_multipoles(const uint64_t* counts, const lc_task* tas
 
 extern "C" lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, int32_t n_tasks,
                                  const int64_t* cat_sizes, int32_t n_cat, const int32_t* est, int32_t n_sub,
-                                 int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, void* stream) {
+                                 int32_t n_mock, int32_t n_r, int32_t n_mu, double* xi, int64_t ld_xi,
+                                 void* stream) {
     clear_error();
     if (n_mock < 0) return fail(LC_ERR_INVALID, "n_mock < 0");
     if (n_mock == 0) return LC_OK;
     if (!counts || !tasks || !cat_sizes || !est || !xi) return fail(LC_ERR_INVALID, "NULL argument");
+    const int64_t P = int64_t(n_r) * n_mu + 3 * int64_t(n_r);
+    if (ld_xi == 0) ld_xi = P;
+    if (ld_xi < P) return fail(LC_ERR_INVALID, "ld_xi = %lld < P = %lld", (long long)ld_xi, (long long)P);
     if (n_sub < 1 || n_sub > 4096) return fail(LC_ERR_INVALID, "n_sub = %d out of [1, 4096]", n_sub);
     if (n_r < 1 || n_mu < 1 || n_mu > LC_MAX_NMU || int64_t(n_r) * n_mu > LC_MAX_BINS)
         return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
@@ -235,7 +239,7 @@ extern "C" lc_status lc_xi_split(const uint64_t* counts, const lc_task* tasks, i
     k_xi_split<<<int((n + threads - 1) / threads), threads, 0, s>>>(
         reinterpret_cast<const unsigned long long*>(counts), reinterpret_cast<const int32_t*>(base + o_est),
         reinterpret_cast<const double*>(base + o_norm), reinterpret_cast<const double*>(base + o_w), n_mock,
-        n_sub, n_r, n_mu, xi);
+        n_sub, n_r, n_mu, ld_xi, xi);
     hipError_t e = hipGetLastError();
     dev_free(dev, s);
     if (e != hipSuccess) return fail(LC_ERR_HIP, "xi launch failed: %s", hipGetErrorString(e));

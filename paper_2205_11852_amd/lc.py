@@ -22,7 +22,7 @@ LC_OK, LC_ERR_INVALID, LC_ERR_RANGE, LC_ERR_OVERFLOW, LC_ERR_HIP, LC_ERR_NOMEM =
 LC_LOS_Z, LC_LOS_MID = 0, 1
 LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
 LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED = 0, 1, 2
-LC_MAX_BINS, LC_MAX_NMU = 8192, 1024
+LC_MAX_BINS, LC_MAX_NMU = 32768, 1024
 
 STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ERR_OVERFLOW",
                 -4: "LC_ERR_HIP", -5: "LC_ERR_NOMEM"}
@@ -30,7 +30,8 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ER
 # the exported symbols of include/lc.h
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
            "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance", "lc_covcov",
-           "lc_autotune", "lc_release_caches"]
+           "lc_autotune", "lc_covariance_general", "lc_rebin_counts", "lc_map_vectors", "lc_map_matrix",
+           "lc_release_caches"]
 
 
 class LcLibraryMissing(RuntimeError):
@@ -134,7 +135,17 @@ def lib():
     L.lc_covariance.argtypes = [vp, i32, i32, i32, i32, ctypes.c_double, i32, vp, vp, vp,
                                 ctypes.POINTER(lc_cov_report), vp]
     L.lc_xi_split.restype = st
-    L.lc_xi_split.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, i32, vp, vp]
+    L.lc_xi_split.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, i32, vp, i64, vp]
+    dbl = ctypes.c_double
+    L.lc_covariance_general.restype = st
+    L.lc_covariance_general.argtypes = [vp, i32, i32, i32, dbl, dbl, dbl, i32, vp, vp, vp,
+                                        ctypes.POINTER(lc_cov_report), vp]
+    L.lc_rebin_counts.restype = st
+    L.lc_rebin_counts.argtypes = [vp, i32, i32, i32, i32, i32, vp, vp]
+    L.lc_map_vectors.restype = st
+    L.lc_map_vectors.argtypes = [vp, i64, i32, i64, vp, vp, i32, vp, i64, vp]
+    L.lc_map_matrix.restype = st
+    L.lc_map_matrix.argtypes = [vp, i32, vp, vp, i32, vp, vp]
     L.lc_sample_covariance.restype = st
     L.lc_sample_covariance.argtypes = [vp, i32, i32, i32, vp, vp]
     L.lc_covcov.restype = st
@@ -291,14 +302,56 @@ def lc_covariance(xi, n_mock: int, n_r: int, n_mu: int, m_a: int, M: float, prec
     return rep.as_dict() if rep is not None else None
 
 
-def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, xi, stream=None):
+def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, xi, stream=None,
+                ld_xi: int = 0, offset: int = 0):
     """est: [n_mock][1 + 2 n_sub] task ids (DD, DR_1..DR_M, RR_1..RR_M);
-    xi: float64 device tensor [n_mock, P]."""
+    xi: float64 device tensor; row n written at element offset + n ld_xi
+    (ld_xi = 0: rows of P back to back)."""
     t = tasks_array(tasks)
     sz = np.ascontiguousarray(np.asarray(cat_sizes, dtype=np.int64))
     e = np.ascontiguousarray(np.asarray(est, dtype=np.int32).reshape(-1, 1 + 2 * int(n_sub)))
     _check(lib().lc_xi_split(_dptr(counts), t.ctypes.data, len(t), sz.ctypes.data, len(sz), e.ctypes.data,
-                             int(n_sub), len(e), int(n_r), int(n_mu), _dptr(xi), _stream(stream)))
+                             int(n_sub), len(e), int(n_r), int(n_mu), _dptr(xi) + 8 * int(offset), int(ld_xi),
+                             _stream(stream)))
+
+
+def lc_covariance_general(xi, n_mock: int, P: int, n_split: int, m_a: float, m_b: float, M: float,
+                          precision: int, A, B, C, report: bool = True, stream=None) -> Optional[dict]:
+    rep = lc_cov_report() if report else None
+    _check(lib().lc_covariance_general(_dptr(xi), int(n_mock), int(P), int(n_split), float(m_a), float(m_b),
+                                       float(M), int(precision), _dptr(A), _dptr(B), _dptr(C),
+                                       ctypes.byref(rep) if rep is not None else None, _stream(stream)))
+    return rep.as_dict() if rep is not None else None
+
+
+def lc_rebin_counts(counts, n_tasks: int, n_r: int, n_mu: int, w_r: int, w_mu: int, out, stream=None):
+    _check(lib().lc_rebin_counts(_dptr(counts), int(n_tasks), int(n_r), int(n_mu), int(w_r), int(w_mu),
+                                 _dptr(out), _stream(stream)))
+
+
+def _map_arrays(group, weight):
+    g = np.ascontiguousarray(np.asarray(group, dtype=np.int32))
+    w = np.ascontiguousarray(np.asarray(weight, dtype=np.float64))
+    if g.shape != w.shape or g.ndim != 1:
+        raise ValueError("group and weight must be 1-D arrays of the same length")
+    return g, w
+
+
+def lc_map_vectors(x, n_vec: int, P_in: int, group, weight, P_out: int, y, ld_x: int = 0, ld_y: int = 0,
+                   stream=None):
+    g, w = _map_arrays(group, weight)
+    if len(g) != P_in:
+        raise ValueError("group has %d entries, P_in = %d" % (len(g), P_in))
+    _check(lib().lc_map_vectors(_dptr(x), int(n_vec), int(P_in), int(ld_x), g.ctypes.data, w.ctypes.data,
+                                int(P_out), _dptr(y), int(ld_y), _stream(stream)))
+
+
+def lc_map_matrix(X, P_in: int, group, weight, P_out: int, Y, stream=None):
+    g, w = _map_arrays(group, weight)
+    if len(g) != P_in:
+        raise ValueError("group has %d entries, P_in = %d" % (len(g), P_in))
+    _check(lib().lc_map_matrix(_dptr(X), int(P_in), g.ctypes.data, w.ctypes.data, int(P_out), _dptr(Y),
+                               _stream(stream)))
 
 
 def lc_sample_covariance(x, n_mock: int, P: int, precision: int, C, stream=None):

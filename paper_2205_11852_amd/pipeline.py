@@ -54,6 +54,50 @@ def plan_direct_tasks(mocks: Sequence[int], subsets: Sequence[int]) -> Tuple[np.
     return np.array(tasks, dtype=np.int32).reshape(-1, 2), np.array(est, dtype=np.int32)
 
 
+def multipole_map(n_r: int, n_mu: int, w: int = 1, r_lo: int = 0, r_hi: Optional[int] = None,
+                  ells: Sequence[int] = (0, 2, 4)) -> Tuple[np.ndarray, np.ndarray, int]:
+    """Map (group, weight, P_out) for lc_map_vectors / lc_map_matrix from the
+    data vector [xi(r, mu) | xi_0 | xi_2 | xi_4] to the multipoles `ells` over
+    r bins [r_lo, r_hi), each output the mean of w adjacent r bins (the last
+    group of a range that w does not divide is narrower).  w = 1 selects, as
+    the 540-element vector of the paper's slabs (r = 20 .. 200 Mpc/h in
+    1 Mpc/h bins) does; w > 1 re-bins to wider bins (Table 3)."""
+    r_hi = n_r if r_hi is None else int(r_hi)
+    if not (0 <= r_lo < r_hi <= n_r) or w < 1:
+        raise ValueError("bad r range [%d, %d) or width %d" % (r_lo, r_hi, w))
+    P = n_r * n_mu + 3 * n_r
+    group = np.full(P, -1, dtype=np.int32)
+    weight = np.zeros(P)
+    n_out = (r_hi - r_lo + w - 1) // w
+    for j, ell in enumerate(ells):
+        li = (0, 2, 4).index(ell)
+        for k in range(r_lo, r_hi):
+            gk = (k - r_lo) // w
+            size = min(w, r_hi - r_lo - gk * w)
+            i = n_r * n_mu + li * n_r + k
+            group[i] = j * n_out + gk
+            weight[i] = 1.0 / size
+    return group, weight, len(ells) * n_out
+
+
+def block_rebin_map(n_blocks: int, n: int, w: int) -> Tuple[np.ndarray, np.ndarray, int]:
+    """Map (group, weight, P_out) that averages w adjacent elements within
+    each of n_blocks consecutive blocks of n (e.g. the r bins of each
+    multipole); the last group of a block is narrower when w does not
+    divide n."""
+    if w < 1 or n < 1 or n_blocks < 1:
+        raise ValueError("bad block map sizes")
+    n_out = (n + w - 1) // w
+    group = np.empty(n_blocks * n, dtype=np.int32)
+    weight = np.empty(n_blocks * n)
+    for j in range(n_blocks):
+        for k in range(n):
+            gk = k // w
+            group[j * n + k] = j * n_out + gk
+            weight[j * n + k] = 1.0 / min(w, n - gk * w)
+    return group, weight, n_blocks * n_out
+
+
 class Pipeline:
     """Device-resident catalogues of one workload and the calls of the path."""
 
@@ -185,6 +229,71 @@ class Pipeline:
         x = torch.empty((len(mocks), b.P), dtype=torch.float64, device=self.device)
         lc.lc_xi_split(counts, tasks, self.sizes, est, len(subsets), b.n_r, b.n_mu, x)
         return x, counts, tasks, est
+
+    def general_vectors(self, mocks: Sequence[int], sets: Sequence[Sequence[int]],
+                        tune: Optional[dict] = None):
+        """Three split estimates per listed mock (x, x' and y of the
+        construction from general M_a < M_b, Eq. CovAB), estimate e over the
+        random catalogues sets[e] (the same for every mock).  Counts every
+        needed task in one launch, then one lc_xi_split per estimate into the
+        [n, 3, P] layout.  Returns the device tensor."""
+        torch = self.torch
+        if len(sets) != 3:
+            raise ValueError("need three subset lists: x, x' (ratio M_a) and y (ratio M_b)")
+        union = sorted(set(int(c) for S in sets for c in S))
+        tasks, est = plan_direct_tasks(mocks, union)
+        b = self.binning
+        counts = torch.zeros((len(tasks), b.n_r, b.n_mu), dtype=torch.int64, device=self.device)
+        if tune is None and self.tuned is not None:
+            tune = self.tuned["tune"]
+        lc.lc_pair_count_batch(self.cells, tasks, b, counts, lc.LC_PERSISTENT, tune, None)
+        xi = torch.empty((len(mocks), 3, b.P), dtype=torch.float64, device=self.device)
+        n_u = len(union)
+        for e, S in enumerate(sets):
+            cols = np.array([union.index(int(c)) for c in S])
+            est_e = np.concatenate([est[:, :1], est[:, 1 + cols], est[:, 1 + n_u + cols]], axis=1)
+            lc.lc_xi_split(counts, tasks, self.sizes, est_e, len(S), b.n_r, b.n_mu, xi, ld_xi=3 * b.P,
+                           offset=e * b.P)
+        return xi
+
+    def covariance_general(self, xi, P: int, n_split: int, m_a: float, m_b: float, M: Optional[float] = None,
+                           precision: int = lc.LC_FP32_MFMA, report: bool = True):
+        """lc_covariance_general on [n, 3, P] vectors; returns (A, B, C, report)."""
+        torch = self.torch
+        A, B, C = (torch.empty((P, P), dtype=torch.float64, device=self.device) for _ in range(3))
+        rep = lc.lc_covariance_general(xi, xi.shape[0], P, n_split, m_a, m_b, self.M if M is None else M,
+                                       precision, A, B, C, report)
+        return A, B, C, rep
+
+    def rebinned(self, w_r: int, w_mu: int):
+        """Counts co-added over w_r r bins and w_mu mu bins (lc_rebin_counts)
+        and the matching binning; w_mu = n_mu gives the 1D counts."""
+        b = self.binning
+        n_r2 = (b.n_r + w_r - 1) // w_r
+        out = self.torch.empty((len(self.tasks), n_r2, b.n_mu // w_mu), dtype=self.torch.int64,
+                               device=self.device)
+        lc.lc_rebin_counts(self.counts, len(self.tasks), b.n_r, b.n_mu, w_r, w_mu, out)
+        e = b.edges
+        edges = [int(e[min(k * w_r, b.n_r)]) for k in range(n_r2 + 1)]
+        return out, lc.Binning(edges, b.n_mu // w_mu, bool(b.c.periodic), int(b.c.box_units), int(b.c.los))
+
+    def xi_of(self, counts, binning) -> "object":
+        """lc_xi_multipoles of other counts of the same tasks (e.g. co-added)."""
+        xi = self.torch.empty((self.n_mock, 3, binning.P), dtype=self.torch.float64, device=self.device)
+        lc.lc_xi_multipoles(counts, self.tasks, self.sizes, self.est, binning.n_r, binning.n_mu, xi)
+        return xi
+
+    def map_vectors(self, xi, group, weight, P_out: int):
+        """lc_map_vectors over every estimate row of an [n, 3, P] tensor."""
+        n, q, P = xi.shape
+        y = self.torch.empty((n, q, P_out), dtype=self.torch.float64, device=self.device)
+        lc.lc_map_vectors(xi, n * q, P, group, weight, P_out, y)
+        return y
+
+    def map_matrix(self, X, group, weight, P_out: int):
+        Y = self.torch.empty((P_out, P_out), dtype=self.torch.float64, device=self.device)
+        lc.lc_map_matrix(X, X.shape[0], group, weight, P_out, Y)
+        return Y
 
     # -- host copies ---------------------------------------------------------
     def counts_host(self) -> np.ndarray:

@@ -60,7 +60,7 @@ def _build_status(L, b, n_total=4, offsets=(0, 4), out=True, xyz=0x1000):
     (dict(r_edges=[-1, 10]), lc.LC_ERR_INVALID),             # negative edge
     (dict(n_mu=0), lc.LC_ERR_INVALID),
     (dict(n_mu=lc.LC_MAX_NMU + 1), lc.LC_ERR_INVALID),
-    (dict(r_edges=list(range(0, 2 * 4097, 2)), n_mu=3), lc.LC_ERR_INVALID),   # too many bins
+    (dict(r_edges=list(range(0, 34)), n_mu=1024), lc.LC_ERR_INVALID),         # too many bins (33 x 1024)
     (dict(r_edges=[0, 10, 500]), lc.LC_ERR_RANGE),           # r_max >= box/2
     (dict(box_units=999), lc.LC_ERR_INVALID),                # odd box
     (dict(box_units=(1 << 24) + 2), lc.LC_ERR_INVALID),
@@ -156,11 +156,15 @@ def test_xi_split_and_sample_covariance_reject_bad_arguments(L):
     sizes = np.array([10, 10], dtype=np.int64)
     good = np.array([[0, 1, 2]], dtype=np.int32)
     assert L.lc_xi_split(0x1000, tasks.ctypes.data, 3, sizes.ctypes.data, 2, good.ctypes.data, 0, 1, 3, 4,
-                         0x2000, None) == lc.LC_ERR_INVALID
+                         0x2000, 0, None) == lc.LC_ERR_INVALID
     swapped = np.array([[0, 2, 1]], dtype=np.int32)
     assert L.lc_xi_split(0x1000, tasks.ctypes.data, 3, sizes.ctypes.data, 2, swapped.ctypes.data, 1, 1, 3, 4,
-                         0x2000, None) == lc.LC_ERR_INVALID
+                         0x2000, 0, None) == lc.LC_ERR_INVALID
     assert "subset" in lc.last_error()
+    # a row stride shorter than the vector (P = 3*4 + 3*3 = 21)
+    assert L.lc_xi_split(0x1000, tasks.ctypes.data, 3, sizes.ctypes.data, 2, good.ctypes.data, 1, 1, 3, 4,
+                         0x2000, 20, None) == lc.LC_ERR_INVALID
+    assert "ld_xi" in lc.last_error()
     assert L.lc_sample_covariance(0x1000, 1, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_sample_covariance(0x1000, 5, 10, 7, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_sample_covariance(None, 5, 10, lc.LC_FP64, 0x2000, None) == lc.LC_ERR_INVALID
@@ -172,3 +176,56 @@ def test_covcov_rejects_bad_arguments(L):
     assert L.lc_covcov(0x1000, 0x2000, 4, 0, 50.0, None, 10, None, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
     assert L.lc_covcov(0x1000, 0x2000, 4, 1, -1.0, None, 10, None, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
     assert L.lc_covcov(0x1000, 0x2000, 4, 1, 50.0, None, 1, 0x3000, None, ctypes.byref(rep), None) == lc.LC_ERR_INVALID
+
+
+def test_covariance_general_rejects_bad_arguments(L):
+    rep = lc.lc_cov_report()
+    ok = dict(xi=0x1000, n=10, P=8, split=4, ma=1.0, mb=3.0, M=50.0, prec=lc.LC_FP64)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.lc_covariance_general(a["xi"], a["n"], a["P"], a["split"], a["ma"], a["mb"], a["M"], a["prec"],
+                                       None, None, 0x2000, ctypes.byref(rep), None)
+
+    assert call(xi=None) == lc.LC_ERR_INVALID
+    assert call(n=1) == lc.LC_ERR_INVALID
+    assert call(P=0) == lc.LC_ERR_INVALID
+    assert call(split=9) == lc.LC_ERR_INVALID and "n_split" in lc.last_error()
+    assert call(split=-1) == lc.LC_ERR_INVALID
+    assert call(mb=1.0) == lc.LC_ERR_INVALID and "m_a" in lc.last_error()
+    assert call(ma=0.0) == lc.LC_ERR_INVALID
+    assert call(mb=float("inf")) == lc.LC_ERR_INVALID
+    assert call(M=0.0) == lc.LC_ERR_INVALID
+    assert call(prec=9) == lc.LC_ERR_INVALID
+
+
+def test_rebin_counts_rejects_bad_arguments(L):
+    assert L.lc_rebin_counts(0x1000, 3, 10, 6, 0, 1, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_rebin_counts(0x1000, 3, 10, 6, 11, 1, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_rebin_counts(0x1000, 3, 10, 6, 2, 4, 0x2000, None) == lc.LC_ERR_INVALID
+    assert "divide" in lc.last_error()
+    assert L.lc_rebin_counts(0x1000, 3, 10, 6, 2, 3, 0x1000, None) == lc.LC_ERR_INVALID
+    assert "alias" in lc.last_error()
+    assert L.lc_rebin_counts(None, 3, 10, 6, 2, 3, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_rebin_counts(None, 0, 10, 6, 2, 3, None, None) == lc.LC_OK   # nothing to do
+
+
+def test_map_calls_reject_bad_arguments(L):
+    g = np.array([0, 0, 1, -1], dtype=np.int32)
+    w = np.array([0.5, 0.5, 1.0, 1.0])
+    assert L.lc_map_vectors(0x1000, 0, 4, 0, g.ctypes.data, w.ctypes.data, 2, 0x2000, 0, None) == lc.LC_OK
+    bad = np.array([0, 2, 1, -1], dtype=np.int32)
+    assert L.lc_map_vectors(0x1000, 5, 4, 0, bad.ctypes.data, w.ctypes.data, 2, 0x2000, 0, None) == lc.LC_ERR_INVALID
+    assert "group[1]" in lc.last_error()
+    wn = np.array([0.5, np.nan, 1.0, 1.0])
+    assert L.lc_map_vectors(0x1000, 5, 4, 0, g.ctypes.data, wn.ctypes.data, 2, 0x2000, 0, None) == lc.LC_ERR_INVALID
+    # a NaN weight on a dropped element is never used
+    wd = np.array([0.5, 0.5, 1.0, np.nan])
+    assert L.lc_map_vectors(0x1000, 0, 4, 0, g.ctypes.data, wd.ctypes.data, 2, 0x2000, 0, None) == lc.LC_OK
+    assert L.lc_map_vectors(0x1000, 5, 4, 3, g.ctypes.data, w.ctypes.data, 2, 0x2000, 0, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_vectors(0x1000, 5, 4, 0, g.ctypes.data, w.ctypes.data, 2, 0x1000, 0, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_vectors(0x1000, 5, 4, 0, None, w.ctypes.data, 2, 0x2000, 0, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_matrix(0x1000, 4, g.ctypes.data, w.ctypes.data, 0, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_matrix(0x1000, 4, bad.ctypes.data, w.ctypes.data, 2, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_matrix(None, 4, g.ctypes.data, w.ctypes.data, 2, 0x2000, None) == lc.LC_ERR_INVALID
+    assert L.lc_map_matrix(0x1000, 4, g.ctypes.data, w.ctypes.data, 2, 0x1000, None) == lc.LC_ERR_INVALID

@@ -133,6 +133,44 @@ def test_c2_count_totals(c2):
     assert np.all(tot <= cap) and np.all(tot > 0)
 
 
+@pytest.fixture(scope="module")
+def slab(torch, lcmod):
+    """Ten full-size paper-shaped slabs (156 158 points on average), counted
+    in one persistent launch with the library defaults."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    wl = dataclasses.replace(mockgen.WORKLOADS["slab"], n_mock=10)
+    _say("[slab] generating", wl.n_mock, "slabs")
+    cats = mockgen.make_catalogues(wl)
+    pl = Pipeline(cats)
+    pl.build_cells()
+    pl.count()
+    torch.cuda.synchronize()
+    _say("[slab] counted %d tasks" % len(pl.tasks))
+    return dict(pl=pl, cats=cats, counts=pl.counts_host().copy())
+
+
+def test_slab_full_size_sampled_tasks(slab, oracle_mod):
+    """DD, DR1 and RR1 of one full-size slab, brute force, bit for bit."""
+    pl, cats = slab["pl"], slab["cats"]
+    wl = cats.wl
+    m = 3
+    for t in pl.est[m][[0, 1, 3]]:
+        a, b = pl.tasks[t]
+        _say("[slab] oracle task", int(t), (int(a), int(b)), cats.sizes()[a], cats.sizes()[b])
+        ref = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units,
+                                     wl.n_mu, 0, "z")
+        assert np.array_equal(slab["counts"][t], ref), int(t)
+
+
+def test_slab_counts_independent_of_tiling(slab, torch):
+    pl = slab["pl"]
+    pl.build_cells(int(75.0 * mockgen.UNITS_PER_MPC), 1)
+    pl.count(tune=dict(chunk=128, waves_per_block=8))
+    torch.cuda.synchronize()
+    assert np.array_equal(pl.counts_host(), slab["counts"])
+    pl.build_cells()
+
+
 def _synthetic_vectors(n_mock, P, seed):
     r = np.random.default_rng(seed)
     L = r.normal(size=(P, P)) / np.sqrt(P) + np.eye(P)

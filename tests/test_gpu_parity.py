@@ -91,7 +91,8 @@ def test_c1_per_mock_baseline_identical(c1, torch):
 @pytest.mark.parametrize("tune", [dict(cells_per_item=1), dict(cells_per_item=7, waves_per_block=1),
                                   dict(waves_per_block=8, blocks_per_cu=1), dict(waves_per_block=2),
                                   dict(chunk=4), dict(chunk=12), dict(chunk=32), dict(chunk=64),
-                                  dict(chunk=20, cells_per_item=3), dict(chunk=128), dict(chunk=256)])
+                                  dict(chunk=20, cells_per_item=3), dict(chunk=128), dict(chunk=256),
+                                  dict(waves_per_block=16), dict(waves_per_block=16, chunk=64, cells_per_item=2)])
 def test_c1_tunings_identical(c1, torch, tune):
     pl = c1["pl"]
     _say("[c1] tune", tune)
@@ -305,6 +306,30 @@ def test_wedge_midpoint_bit_exact(torch, oracle_mod, lcmod):
             assert np.array_equal(gpu[t], ref), (cell_mpc, t)
 
 
+def test_slab_open_geometry_bit_exact(torch, oracle_mod, lcmod):
+    """The paper's slab shape (open 1500 x 1500 x 300 Mpc/h, z line of sight,
+    200 x 100 bins: an 80 KB block histogram) at a density the oracle counts
+    fully, on the default and the autotuned mesh."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    wl = dataclasses.replace(mockgen.WORKLOADS["slab"], n_mock=2, n_mean=6000.0, n_parents=7500)
+    cats = mockgen.make_catalogues(wl)
+    pl = Pipeline(cats)
+    refs = {}
+    for tuned in (False, True):
+        if tuned:
+            pl.autotune(8)
+        pl.build_cells()
+        _say("[slab] grid", pl.cells.info()["grid"], "tuned", tuned)
+        pl.count()
+        torch.cuda.synchronize()
+        gpu = pl.counts_host()
+        for t, (a, b) in enumerate(pl.tasks):
+            if t not in refs:
+                refs[t] = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b),
+                                                 wl.r_edges_units, wl.n_mu, 0, "z")
+            assert np.array_equal(gpu[t], refs[t]), (tuned, t)
+
+
 def test_ragged_catalogues(torch, oracle_mod, lcmod):
     """Empty and one-point catalogues, coincident points, points on the box
     faces, everything in one cell, non-uniform edges with e_0 > 0."""
@@ -435,3 +460,169 @@ def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref):
     v_smp = oracle_mod.sample_cov_element_var(A + (0.0 if np.isinf(M) else 1.0 / M) * B, n)
     assert np.allclose(sd_lc.cpu().numpy(), np.sqrt(v_lc), rtol=1e-12, atol=0)
     assert np.allclose(sd_smp.cpu().numpy(), np.sqrt(v_smp), rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# co-added counts, 1D xi, linear maps and the general construction
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("w_r,w_mu", [(1, 1), (3, 2), (6, 5), (20, 10), (4, 10)])
+def test_rebin_counts_parity(c1, oracle_mod, torch, lcmod, w_r, w_mu):
+    """Co-added counts on the device, bit for bit against the oracle's
+    co-adding of its own counts (ragged r groups, the 1D count, one bin)."""
+    pl = c1["pl"]
+    wl = c1["cats"].wl
+    pl.count()
+    out, b2 = pl.rebinned(w_r, w_mu)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint64)
+    assert list(b2.edges) == oracle_mod.rebinned_edges(wl.r_edges_units, w_r)
+    for t in range(len(pl.tasks)):
+        assert np.array_equal(got[t], oracle_mod.rebin_counts(c1["ref"][t], w_r, w_mu)), t
+
+
+def test_one_dimensional_xi_parity(c1, oracle_mod, torch, lcmod):
+    """The 1D correlation function (counts co-added over mu, Sect. 4.3) and
+    its vector: within 1e-12 of the oracle; xi_2 = xi_4 = 0 exactly."""
+    pl = c1["pl"]
+    wl = c1["cats"].wl
+    pl.count()
+    c, b1 = pl.rebinned(1, wl.n_mu)
+    xi = pl.xi_of(c, b1)
+    torch.cuda.synchronize()
+    g = xi.cpu().numpy()
+    n_r = wl.n_r
+    for m in range(pl.n_mock):
+        e = pl.est[m]
+        D, R1, R2 = pl.tasks[e[0]][0], pl.tasks[e[1]][1], pl.tasks[e[2]][1]
+        V = oracle_mod.mock_vectors(*(oracle_mod.rebin_counts(c1["ref"][t], 1, wl.n_mu) for t in e),
+                                    pl.sizes[D], pl.sizes[R1], pl.sizes[R2])
+        assert np.array_equal(np.isnan(g[m]), np.isnan(V))
+        ok = np.isfinite(V)
+        assert np.allclose(g[m][ok], V[ok], rtol=1e-12, atol=0)
+        assert np.all(g[m][:, 2 * n_r:][ok[:, 2 * n_r:]] == 0.0)
+
+
+def _random_map(r, P_in, P_out):
+    g = r.integers(-1, P_out - 1, size=P_in).astype(np.int32)
+    g[:P_out - 1] = np.arange(P_out - 1)  # every output but the last has a member
+    g[P_out - 1] = -1                     # the last one has none (must be 0)
+    w = r.normal(size=P_in)
+    return g, w
+
+
+def test_map_vectors_and_matrix_parity(torch, oracle_mod, lcmod):
+    """Linear maps on the device against the oracle's dense T (float64,
+    1e-12 of the summed magnitudes); strided rows; an empty output is 0."""
+    r = np.random.default_rng(21)
+    N, P_in, P_out = 37, 300, 61
+    X = r.normal(size=(N, 3, P_in))
+    g, w = _random_map(r, P_in, P_out)
+    x = torch.from_numpy(X).cuda()
+    y = torch.full((N, 3, P_out + 5), 7.0, dtype=torch.float64, device="cuda")
+    lcmod.lc_map_vectors(x, 3 * N, P_in, g, w, P_out, y, ld_y=P_out + 5)
+    torch.cuda.synchronize()
+    gy = y.cpu().numpy()
+    ref = oracle_mod.map_vectors(X, g, w, P_out)
+    scale = oracle_mod.map_vectors(np.abs(X), g, np.abs(w), P_out)
+    assert np.all(np.abs(gy[..., :P_out] - ref) <= 1e-12 * scale + 1e-300)
+    assert np.all(gy[..., P_out:] == 7.0)            # the stride gap is untouched
+    assert np.all(gy[..., P_out - 1] == 0.0)
+    # the selection map of the paper's multipole vector picks elements exactly
+    from paper_2205_11852_amd.pipeline import multipole_map
+    gs, ws, Ps = multipole_map(20, 10, 1, 4, 20)
+    xs = torch.from_numpy(r.normal(size=(5, 3, 20 * 10 + 60))).cuda()
+    ys = torch.empty((5, 3, Ps), dtype=torch.float64, device="cuda")
+    lcmod.lc_map_vectors(xs, 15, xs.shape[2], gs, ws, Ps, ys)
+    torch.cuda.synchronize()
+    assert np.array_equal(ys.cpu().numpy(), oracle_mod.map_vectors(xs.cpu().numpy(), gs, ws, Ps))
+    # matrices
+    S = r.normal(size=(P_in, P_in))
+    S = S + S.T
+    Y = torch.empty((P_out, P_out), dtype=torch.float64, device="cuda")
+    lcmod.lc_map_matrix(torch.from_numpy(S).cuda(), P_in, g, w, P_out, Y)
+    torch.cuda.synchronize()
+    refY = oracle_mod.map_matrix(S, g, w, P_out)
+    scY = oracle_mod.map_matrix(np.abs(S), g, np.abs(w), P_out)
+    gY = Y.cpu().numpy()
+    assert np.all(np.abs(gY - refY) <= 1e-12 * scY + 1e-300)
+    assert np.all(gY[P_out - 1] == 0.0) and np.all(gY[:, P_out - 1] == 0.0)
+
+
+@pytest.mark.parametrize("m_a,m_b,n_split", [(1.0, 3.0, 100), (2.0, 5.0, 0), (0.5, 4.0, 160), (1.0, 2.0, 37)])
+def test_covariance_general_parity(torch, oracle_mod, lcmod, m_a, m_b, n_split):
+    """Eq. CovAB on the device: float64 within 1e-12 and float32 MFMA within
+    1e-5 of the oracle; the check of both blocks against LAPACK."""
+    n_mock, P = 400, 160
+    V = _synthetic_vectors(n_mock, P, int(10 * m_a + m_b))
+    xi = torch.from_numpy(V).cuda()
+    A, B, C = (torch.empty((P, P), dtype=torch.float64, device="cuda") for _ in range(3))
+    for M in (50.0, float("inf")):
+        rA, rB, rC, _, _ = oracle_mod.lc_from_vectors_general(V, m_a, m_b, M)
+        for prec, tol in ((lcmod.LC_FP64, 1e-12), (lcmod.LC_FP32_MFMA_CHECKED, 1e-5)):
+            rep = lcmod.lc_covariance_general(xi, n_mock, P, n_split, m_a, m_b, M, prec, A, B, C, report=True)
+            torch.cuda.synchronize()
+            gA, gB, gC = (t.cpu().numpy() for t in (A, B, C))
+            assert _rel_frob(gA, rA) < tol and _rel_frob(gB, rB) < tol and _rel_frob(gC, rC) < tol, (M, prec)
+        for blk, sl in enumerate((slice(0, n_split), slice(n_split, P))):
+            if sl.stop - sl.start == 0:
+                assert rep["chol_ok"][blk] == 1 and rep["n_neg_eig"][blk] == 0
+                assert np.isnan(rep["min_eig"][blk]) and np.isnan(rep["max_eig"][blk])
+                continue
+            wv = np.linalg.eigvalsh(gC[sl, sl])
+            scale = np.abs(wv).max()
+            assert abs(rep["min_eig"][blk] - wv[0]) <= 1e-10 * scale
+            assert abs(rep["max_eig"][blk] - wv[-1]) <= 1e-10 * scale
+            assert rep["n_neg_eig"][blk] == int((wv < 0).sum())
+
+
+def test_covariance_general_at_paper_ratios_equals_lc_covariance(c1, c1_cov, torch, lcmod):
+    """With M_b = 2 M_a and the (r, mu) block split, the general call is
+    lc_covariance, bit for bit."""
+    pl = c1["pl"]
+    _load_xi(pl, c1_cov["xi"], torch)
+    P, nb = pl.binning.P, pl.binning.n_r * pl.binning.n_mu
+    pl.covariance(lcmod.LC_FP64, report=False)
+    torch.cuda.synchronize()
+    ref = [t.cpu().numpy().copy() for t in (pl.A, pl.B, pl.C)]
+    A, B, C, _ = pl.covariance_general(pl.xi, P, nb, 1.0, 2.0, precision=lcmod.LC_FP64, report=False)
+    torch.cuda.synchronize()
+    for x, y in zip((A, B, C), ref):
+        x = x.cpu().numpy()
+        assert np.array_equal(np.isnan(x), np.isnan(y))
+        assert np.array_equal(x[np.isfinite(x)], y[np.isfinite(y)])
+
+
+def test_general_vectors_and_strided_split(c1, torch, lcmod, oracle_mod):
+    """Estimates x, x' (M_a = 1) and y (M_b = 2) over the same pool
+    sub-catalogues for every mock, written by lc_xi_split into the [n, 3, P]
+    layout with a row stride, against the oracle's split estimator on the
+    oracle's counts."""
+    pl = c1["pl"]
+    cats = c1["cats"]
+    wl = cats.wl
+    pool = cats.random_catalogue_ids()
+    assert len(pool) >= 2
+    sets = [[pool[0]], [pool[1]], [pool[0], pool[1]]]
+    mocks = list(range(6))
+    W = oracle_mod.legendre_weights(wl.n_mu)
+    xi = pl.general_vectors(mocks, sets)
+    torch.cuda.synchronize()
+    g = xi.cpu().numpy()
+    for m in mocks:
+        dd = c1["ref"][pl.est[m][0]] if pl.tasks[pl.est[m][0]][0] == m else None
+        assert dd is not None
+        for e, S in enumerate(sets):
+            DR = [oracle_mod.count_pairs(cats.cat(m), cats.cat(s), wl.r_edges_units, wl.n_mu, wl.box_units, wl.los)
+                  for s in S]
+            RR = [oracle_mod.count_pairs(cats.cat(s), None, wl.r_edges_units, wl.n_mu, wl.box_units, wl.los)
+                  for s in S]
+            V = oracle_mod.data_vector(oracle_mod.ls_split(dd, DR, RR, pl.sizes[m], [pl.sizes[s] for s in S]))
+            assert np.array_equal(np.isnan(g[m, e]), np.isnan(V))
+            ok = np.isfinite(V)
+            nb = wl.n_r * wl.n_mu
+            assert np.allclose(g[m, e, :nb][ok[:nb]], V[:nb][ok[:nb]], rtol=1e-12, atol=0)
+            x2 = V[:nb].reshape(wl.n_r, wl.n_mu)
+            scale = (np.abs(x2)[:, None, :] * np.abs(W)[None, :, :]).sum(axis=2).T.ravel()
+            fin = np.isfinite(V[nb:])
+            assert np.all(np.abs(g[m, e, nb:] - V[nb:])[fin] <= 1e-12 * scale[fin] + 1e-300)

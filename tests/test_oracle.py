@@ -519,3 +519,125 @@ def test_covcov_summary_consistency(oracle_mod):
     s50 = oracle_mod.covcov_summary(A, B, 1, 50.0)
     assert abs(s50["gain"] - s50["ifom_smp"] / s50["ifom_lc"]) < 1e-12 * s50["gain"]
     assert s50["cost_smp"] == 151.0 and s50["cost_lc"] == 7.0
+
+
+# ---------------------------------------------------------------------------
+# co-added counts, linear maps, general M_a and M_b (Sect. 2.3, 4.3, 5.3)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("box,los", [(1 << 20, "z"), (0, "z"), (0, "mid")])
+def test_rebin_counts_equals_counting_in_wide_bins(oracle_mod, box, los):
+    """Co-added counts are the counts in the wider bins, counted directly by
+    brute force with the co-added edges: for ragged r groups, mu groups that
+    divide n_mu, and the 1D count over all mu (Sect. 4.3)."""
+    lo = 0 if box else 1 << 21
+    a = _rand_pts(31, 500, lo, lo + (1 << 20) if not box else box)
+    b = _rand_pts(32, 400, lo, lo + (1 << 20) if not box else box)
+    edges = np.array([0, 3000, 9000, 20000, 26000, 41000, 60000, 61000], dtype=np.int64)
+    n_mu = 12
+    for bb in (None, b):
+        fine = oracle_mod.count_pairs(a, bb, edges, n_mu, box, los)
+        for w_r, w_mu in ((1, 1), (3, 2), (2, 3), (7, 12), (4, 12), (5, 4)):
+            got = oracle_mod.rebin_counts(fine, w_r, w_mu)
+            e2 = oracle_mod.rebinned_edges(edges, w_r)
+            ref = oracle_mod.count_pairs(a, bb, e2, n_mu // w_mu, box, los)
+            assert np.array_equal(got, ref), (w_r, w_mu)
+            assert got.sum() == fine.sum()
+
+
+def test_rebinned_edges(oracle_mod):
+    assert oracle_mod.rebinned_edges([0, 1, 2, 3, 4, 5, 6, 7], 3) == [0, 3, 6, 7]
+    assert oracle_mod.rebinned_edges([0, 1, 2, 3, 4], 2) == [0, 2, 4]
+    assert oracle_mod.rebinned_edges([5, 9], 1) == [5, 9]
+
+
+def test_one_dimensional_xi_from_co_added_counts(oracle_mod):
+    """The 1D correlation function is the estimator applied to counts
+    co-added over mu (Sect. 4.3); its data vector has xi_0 = xi and
+    xi_2 = xi_4 = 0 exactly (P_2 and P_4 integrate to zero over [0, 1])."""
+    L = 1 << 20
+    d, r1, r2 = _rand_pts(41, 600, 0, L), _rand_pts(42, 600, 0, L), _rand_pts(43, 600, 0, L)
+    edges = np.linspace(0, L // 8, 7).astype(np.int64)
+    c = oracle_mod.mock_counts(d, r1, r2, edges, 10, L, "z")
+    c1 = [oracle_mod.rebin_counts(x, 1, 10) for x in c]
+    V = oracle_mod.mock_vectors(*c1, 600, 600, 600)
+    n_r = len(edges) - 1
+    for q in range(3):
+        xi1 = V[q, :n_r]
+        assert np.array_equal(V[q, n_r:2 * n_r], xi1)
+        assert np.all(V[q, 2 * n_r:] == 0.0)
+    # and it is the estimator of counts made with one mu bin directly
+    direct = oracle_mod.mock_counts(d, r1, r2, edges, 1, L, "z")
+    assert all(np.array_equal(x, y) for x, y in zip(c1, direct))
+
+
+def test_linear_map_small_example(oracle_mod):
+    """Hand-computed: elements 0 and 1 averaged, 2 kept, 3 dropped."""
+    g, w = [0, 0, 1, -1], [0.5, 0.5, 1.0, 1.0]
+    x = np.array([1.0, 3.0, 5.0, 7.0])
+    assert np.array_equal(oracle_mod.map_vectors(x, g, w, 2), [2.0, 5.0])
+    C = np.arange(16.0).reshape(4, 4)
+    # Y_00 = (C00 + C01 + C10 + C11)/4, Y_01 = (C02 + C12)/2, Y_11 = C22
+    Y = oracle_mod.map_matrix(C, g, w, 2)
+    assert np.allclose(Y, [[(0 + 1 + 4 + 5) / 4, (2 + 6) / 2], [(8 + 9) / 2, 10]], rtol=0, atol=1e-15)
+
+
+def test_map_matrix_is_covariance_of_mapped_vectors(oracle_mod):
+    """Cov(T x) = T Cov(x) T^T: re-binning the covariance (Sect. 5.3) equals
+    the covariance of the re-binned vectors."""
+    r = np.random.default_rng(12)
+    P, P_out, N = 30, 11, 200
+    V = r.normal(size=(N, P)) @ r.normal(size=(P, P))
+    g = r.integers(-1, P_out, size=P)
+    w = r.normal(size=P)
+    lhs = oracle_mod.map_matrix(oracle_mod.sample_cov(V), g, w, P_out)
+    rhs = oracle_mod.sample_cov(oracle_mod.map_vectors(V, g, w, P_out))
+    assert np.allclose(lhs, rhs, rtol=1e-11, atol=1e-11 * np.abs(rhs).max())
+
+
+@pytest.mark.parametrize("m_a,m_b", [(1.0, 2.0), (1.0, 3.0), (2.0, 5.0), (0.5, 4.0), (3.0, 6.0)])
+def test_general_construction_recovers_exact_model(oracle_mod, m_a, m_b):
+    """Eq. CovAB: if C(M) = A0 + B0/M exactly, the covariances at M_a and M_b
+    give back A0 and B0, C(M) for any M, and the inputs at M = M_a, M_b."""
+    r = np.random.default_rng(int(10 * m_a + m_b))
+    X, Y = r.normal(size=(6, 6)), r.normal(size=(6, 6))
+    A0, B0 = X @ X.T, Y @ Y.T
+    Ca, Cb = A0 + B0 / m_a, A0 + B0 / m_b
+    for M in (1.0, 7.5, 50.0, np.inf):
+        A, B, C = oracle_mod.linear_construction_general(Ca, Cb, m_a, m_b, M)
+        assert np.allclose(A, A0, rtol=1e-12, atol=1e-12)
+        assert np.allclose(B, B0, rtol=1e-12, atol=1e-12)
+        assert np.allclose(C, A0 if np.isinf(M) else A0 + B0 / M, rtol=1e-12, atol=1e-12)
+    assert np.allclose(oracle_mod.linear_construction_general(Ca, Cb, m_a, m_b, m_a)[2], Ca)
+    assert np.allclose(oracle_mod.linear_construction_general(Ca, Cb, m_a, m_b, m_b)[2], Cb)
+    if m_b == 2 * m_a:
+        ref = oracle_mod.linear_construction(Ca, Cb, int(m_a), 50.0)
+        got = oracle_mod.linear_construction_general(Ca, Cb, m_a, m_b, 50.0)
+        assert all(np.allclose(x, y, rtol=1e-13, atol=0) for x, y in zip(got, ref))
+
+
+def test_general_construction_matches_random_theory(oracle_mod):
+    """Uniform mocks with M_a = 1 (x from R1, x' from R2) and M_b = 3 (y split
+    over R1, R2, R3): the diagonal of C(M) follows the analytic variance for
+    uniform data at M = 1, 3 and 20, and at M = infinity its first term."""
+    n_mock, n, L = 240, 700, 1 << 20
+    xyz, off, ids = mockgen.independent_poisson_mocks(91, n_mock, n, L, n_random=3)
+    edges = np.linspace(L // 40, L // 8, 9).astype(np.int64)
+    V = []
+    for m in range(n_mock):
+        c = [xyz[:, off[i]:off[i + 1]] for i in ids[m]]
+        DD = oracle_mod.count_pairs(c[0], None, edges, 1, L, "z")
+        DR = [oracle_mod.count_pairs(c[0], c[1 + k], edges, 1, L, "z") for k in range(3)]
+        RR = [oracle_mod.count_pairs(c[1 + k], None, edges, 1, L, "z") for k in range(3)]
+        V.append([oracle_mod.ls_split(DD, DR[:1], RR[:1], n, [n]).ravel(),
+                  oracle_mod.ls_split(DD, DR[1:2], RR[1:2], n, [n]).ravel(),
+                  oracle_mod.ls_split(DD, DR, RR, n, [n] * 3).ravel()])
+    V = np.array(V)
+    G_p = oracle_mod.shell_pair_fraction(edges, 1, L).ravel()
+    A, B, _, _, _ = oracle_mod.lc_from_vectors_general(V, 1.0, 3.0, 50.0)
+    for M, tol in ((1.0, 0.08), (3.0, 0.1), (20.0, 0.2), (np.inf, 0.3)):
+        CM = A if np.isinf(M) else A + B / M
+        theory = (2.0 / (n * (n - 1.0)) / G_p if np.isinf(M)
+                  else oracle_mod.random_theory_variance(n, M * n, G_p))
+        ratio = np.diag(CM) / theory
+        assert abs(ratio.mean() - 1.0) < tol, (M, ratio)
