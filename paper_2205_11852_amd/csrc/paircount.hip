@@ -61,7 +61,10 @@ struct PcParams {
     int32_t queue_byte0;    // LDS byte offset of wave 0's queue
     int32_t pad2;
     float emax2_hi, emin2_lo;   // phase A acceptance (float32, with margin)
-    float inv_drf, e0_over_drf, nmuf, eps_r, eps_m;
+    float inv_drf, nmuf;
+    // estimates shifted down by their margins and the single-compare bounds
+    // on their fractions (see bin_fast)
+    float r_shift, ok_r, mu_shift, ok_m;
     uint32_t wave_limit;        // candidate tests a wave may register between flushes
     uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
@@ -208,10 +211,16 @@ __device__ __forceinline__ void wave_sync_lds() {
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ int bin_fast(const float4 e, const int* __restrict__ itab, const PcParams& p,
                                         bool& ok) {
+    // Each estimate is shifted down by its margin eps inside the FMA that
+    // forms it, x' = x - eps.  Then fract(x') < 1 - 2 eps (one compare)
+    // holds only when x lies in (floor(x') + eps', floor(x') + 1 - eps') with
+    // eps' = eps minus the estimate's own error, i.e. strictly inside the
+    // bin floor(x').  A shifted value below 0 (x within eps of 0) has a
+    // fraction near 1 and fails, and so does NaN.
     float d2f, u;
     if (LOS == 0) {
         d2f = e.w;
-        u = fabsf(e.z) * __builtin_amdgcn_rsqf(d2f) * p.nmuf;
+        u = fmaf(fabsf(e.z) * __builtin_amdgcn_rsqf(d2f), p.nmuf, -p.mu_shift);
     } else {
         // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
         // exact in float64 (< 2^53)
@@ -222,23 +231,21 @@ __device__ __forceinline__ int bin_fast(const float4 e, const int* __restrict__ 
         const double P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
         const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
         d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
-        u = fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)) *
-            p.nmuf;
+        u = fmaf(fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)),
+                 p.nmuf, -p.mu_shift);
     }
-    // |mu| n_mu <= n_mu exactly; an estimate at or above n_mu - eps_m (mu near
-    // 1) fails the test below, so m < n_mu whenever ok
+    // |mu| n_mu <= n_mu exactly; an estimate within eps_m of n_mu (mu near 1)
+    // fails the test below, so m < n_mu whenever ok
     const int m = int(u);
-    const float fm = __builtin_amdgcn_fractf(u);
-    ok = (fm > p.eps_m) & (fm < 1.0f - p.eps_m);
+    ok = __builtin_amdgcn_fractf(u) < p.ok_m;
     int k = 0;
     if (UNIFORM) {
         // eps_r also covers phase A's acceptance margin, so a pair outside
         // [e_0, e_n) never passes this test with k outside [0, n_r)
         const float r = d2f * __builtin_amdgcn_rsqf(d2f);
-        const float t = HAS_E0 ? fmaf(r, p.inv_drf, -p.e0_over_drf) : r * p.inv_drf;
+        const float t = fmaf(r, p.inv_drf, -p.r_shift);
         k = int(t);
-        const float fr = __builtin_amdgcn_fractf(t);
-        ok = ok & (fr > p.eps_r) & (fr < 1.0f - p.eps_r);
+        ok = ok & (__builtin_amdgcn_fractf(t) < p.ok_r);
     } else {
         ok = false;  // non-uniform edges: every pair takes the integer rule
     }
@@ -829,30 +836,34 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.emax2_hi = f32_up(double(emax2) * (1.0 + std::ldexp(1.0, -20)));
     p.emin2_lo = f32_down(double(emin2) * (1.0 - std::ldexp(1.0, -20)));
     p.inv_drf = float(1.0 / double(de));
-    p.e0_over_drf = float(double(e0) / double(de));
     p.nmuf = float(n_mu);
     // Float32 error bounds in units of u = 2^-24 (relative error per rounding;
     // v_rsq_f32 is within 1 ulp = 2u):
     //   d2 (float32 sum of exact squares): 3u
-    //   mu estimate |s_z| rsq(d2) n_mu: 1.5u (from d2) + 2u + two products 2u
-    //     -> 5.5u n_mu absolute; midpoint: p and q conversions, rsq(q), one
-    //     more product -> 10u n_mu
-    //   r estimate d2 rsq(d2): 1.5u + 2u + 1u = 4.5u of r; t = r/de - e0/de by
-    //     one fma with rounded 1/de and e0/de -> u (5.5 r_max + e0)/de + u n_r
+    //   mu estimate |s_z| rsq(d2) n_mu - eps_m: 1.5u (from d2) + 2u + a product
+    //     and an fma 2u -> 5.5u n_mu absolute; midpoint: p and q conversions,
+    //     rsq(q), one more product -> 10u n_mu
+    //   r estimate d2 rsq(d2): 1.5u + 2u + 1u = 4.5u of r; t = r/de - (e0/de +
+    //     eps_r) by one fma with rounded 1/de and a rounded shift ->
+    //     u (5.5 r_max + e0)/de + u (n_r + 1)
     // The margins are 4x these bounds; pairs closer to an edge take the
     // integer rule.
     const double u = std::ldexp(1.0, -24);
     const double em = (mid ? 10.0 : 5.5) * u * n_mu;
-    p.eps_m = f32_up(std::max(4.0 * em, std::ldexp(1.0, -22)));
-    const double er = u * ((5.5 * double(rmax) + double(e0)) / double(de) + double(n_r));
+    const float eps_m = f32_up(std::max(4.0 * em, std::ldexp(1.0, -22)));
+    const double er = u * ((5.5 * double(rmax) + double(e0)) / double(de) + double(n_r) + 1.0);
     // plus the distance of an accepted pair outside [e_0, e_n) from the edge:
     // phase A accepts d2 < e_n^2 (1 + 2^-20) and d2 >= e_0^2 (1 - 2^-20), i.e.
     // |r - edge| < 2^-20 edge, which is at most 2^-20 r_max / de in units of t
     const double margin_t = std::ldexp(double(rmax) / double(de), -20);
-    p.eps_r = f32_up(std::max(4.0 * er + 2.0 * margin_t, std::ldexp(1.0, -22)));
-    // LC_FORCE_EXACT: no fraction lies in (eps_r, 1 - eps_r) once eps_r >= 1,
-    // so every pair takes the integer rule
-    if (mode & LC_FORCE_EXACT) p.eps_r = 2.0f;
+    const float eps_r = f32_up(std::max(4.0 * er + 2.0 * margin_t, std::ldexp(1.0, -22)));
+    p.mu_shift = eps_m;
+    p.ok_m = f32_down(1.0 - 2.0 * double(eps_m));
+    p.r_shift = float(double(e0) / double(de) + double(eps_r));
+    p.ok_r = f32_down(1.0 - 2.0 * double(eps_r));
+    // LC_FORCE_EXACT: no fraction is below a negative bound, so every pair
+    // takes the integer rule
+    if (mode & LC_FORCE_EXACT) p.ok_r = -1.0f;
     const bool has_emin = e0 > 0;
     pl.kern = pick_kernel(mid ? 1 : 0, uniform, has_emin);
     pl.mode = mode;
