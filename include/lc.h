@@ -135,9 +135,10 @@ typedef struct { int32_t cat_a, cat_b; } lc_task;
 /* Tuning knobs; NULL or 0 fields = library defaults. */
 typedef struct {
     int32_t cells_per_item;   /* cells of one catalogue per work item */
-    int32_t waves_per_block;  /* 1, 2, 4, 8, 16 (default: the shape with the most resident waves per CU,
-                                 4 unless a large histogram leaves LDS for one block only): waves sharing
-                                 a work item and a histogram */
+    int32_t waves_per_block;  /* 1, 2, 4, 8, 16: waves sharing a work item and a histogram.  Default:
+                                 batched, the shape with the most resident waves per CU (4, unless a
+                                 large histogram leaves LDS for one block only); LC_PER_TASK, 16 (a
+                                 single task's few items finish sooner with more waves each) */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
     int32_t chunk;            /* i points tested together against each gathered j set:
                                  a multiple of 4 in [4, 256] ([4, 64] for LC_LOS_MID);
@@ -363,13 +364,14 @@ typedef struct {
 
 /*
  * lc_autotune: choose the mesh (cell side, sub-cell split) and the launch
- * shape (i points per gather, waves per block) for a batch of tasks by
- * timing them.
+ * shape (i points per gather) for a batch of tasks by timing them.
  * Pair counts do not depend on these choices (they are exact); only the time
  * does, through the number of candidate tests and the cost of gathering
  * neighbour cells.  Candidates: cell sides r_max / k (k = 1, 1.5, 2, 3, 4) and
  * the default, each with sub-cell splits 1, 2 and 4; then chunks of i points
- * for the best mesh, then 4, 8 and 16 waves per block.  Each is timed with HIP events over `sample_tasks` tasks
+ * for the best mesh.  (Waves per block keep the library default: a sample
+ * of the tasks does not predict that choice for the whole batch.)  Each is
+ * timed with HIP events over `sample_tasks` tasks
  * spread evenly over the list (one untimed launch, then two timed).
  *   xyz, n_total, cat_offsets, n_cat, b   as for lc_build_cells.
  *   tasks     HOST [n_tasks], as for lc_pair_count_batch.

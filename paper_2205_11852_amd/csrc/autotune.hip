@@ -194,21 +194,6 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
                     best.tune = tn;
                 }
             }
-            // stage 3: waves per block (waves sharing one histogram) at the
-            // chosen chunk; the default shape was timed above
-            for (int wpb : {4, 8, 16}) {
-                if (st != LC_OK) break;
-                lc_tuning tn = best.tune;
-                tn.waves_per_block = wpb;
-                double ms = 0.0;
-                st = time_launch(c, sample, b, counts, tn, s, e0, e1, 2, &ms);
-                if (st != LC_OK) break;
-                tried++;
-                if (ms < best.sample_ms) {
-                    best.sample_ms = ms;
-                    best.tune = tn;
-                }
-            }
             lc_free_cells(c);
         }
     }

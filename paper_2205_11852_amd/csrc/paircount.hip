@@ -884,6 +884,13 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
             return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4, 8 or 16", wpb);
         while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
         LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
+    } else if (mode & LC_PER_TASK) {
+        // one task per launch has few items: the largest blocks finish each
+        // item soonest, which shortens the launch's tail (1000 c2 mocks: 2.85 s
+        // with 16 waves per block against 4.30 s with 4)
+        wpb = 16;
+        while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
+        LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
     } else {
         // the block shape that keeps the most waves resident per CU, the
         // smallest on a tie: a small histogram leaves room for several
