@@ -23,6 +23,12 @@
  *          d2 = 0 or q = 0 -> m = 0
  *     counts[k][m] += 1
  *
+ *   (r_p, pi) binning (plane-parallel along z; the binning of the projected
+ *   correlation function, Sect. 2.3): the same loops with
+ *     r_p-bin k: e_k^2 <= s_x^2 + s_y^2 < e_{k+1}^2
+ *     pi-bin m: pairs with |s_z| >= pi_max dropped, else
+ *          m = floor(n_pi |s_z| / pi_max) (integer division)
+ *
  * All comparisons are exact integer arithmetic in unsigned 128 bits.  The
  * loops are the plain O(N_a N_b) enumeration, parallelised over i only.
  */
@@ -77,13 +83,13 @@ static inline int mu_bin_mid(uint64_t d2, const int64_t s[3], const int64_t l[3]
 /*
  * a, b: SoA int32 coordinates, x[0..n) then y[0..n) then z[0..n).
  * box: periodic side in units (> 0, even), or 0 for open geometry.
- * los: 0 plane-parallel z, 1 midpoint.
+ * los: 0 plane-parallel z, 1 midpoint, 2 (r_p, pi) along z with pi_max.
  * edges: n_r + 1 strictly increasing non-negative integers.
  * counts: uint64 [n_r][n_mu], overwritten.
  * n_threads <= 0: OpenMP default.  Returns the thread count used.
  */
 int oracle_count_pairs(const int32_t* a, int64_t na, const int32_t* b, int64_t nb,
-                       int auto_pairs, int64_t box, int los,
+                       int auto_pairs, int64_t box, int los, int64_t pi_max,
                        int n_r, const int64_t* edges, int n_mu,
                        uint64_t* counts, int n_threads) {
     const int nbins = n_r * n_mu;
@@ -108,6 +114,14 @@ int oracle_count_pairs(const int32_t* a, int64_t na, const int32_t* b, int64_t n
                 const int64_t xj[3] = {b[j], b[nb + j], b[2 * nb + j]};
                 int64_t s[3];
                 for (int c = 0; c < 3; c++) s[c] = wrap(xj[c] - xi[c], box);
+                if (los == 2) {
+                    const uint64_t rp2 = (uint64_t)(s[0] * s[0]) + (uint64_t)(s[1] * s[1]);
+                    const int kp = r_bin(rp2, e2, n_r);
+                    const uint64_t az = uabs64(s[2]);
+                    if (kp < 0 || az >= (uint64_t)pi_max) continue;
+                    h[kp * n_mu + (int)(((uint64_t)n_mu * az) / (uint64_t)pi_max)]++;
+                    continue;
+                }
                 uint64_t d2 = (uint64_t)(s[0] * s[0]) + (uint64_t)(s[1] * s[1]) +
                               (uint64_t)(s[2] * s[2]);
                 int k = r_bin(d2, e2, n_r);

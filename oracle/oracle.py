@@ -24,6 +24,8 @@ Everything below is the plain definition from the paper, in float64:
   (Sect. 3.2, 3.3): element variances of the sample and of the LC
   covariance, and their summaries chi^2_2, pair-count cost and inverse
   figure of merit (Sect. 5.3, Table 3);
+* pair counts binned in (r_p, pi) along z (``count_pairs`` with los
+  "rppi") and the projected correlation function w_p (Sect. 2.3);
 * co-added (re-binned) pair counts, including the 1D count over all mu
   (Sect. 4.3); linear maps of data vectors and covariances (re-binning,
   selection; Sect. 2.3, 5.3); the construction from general M_a < M_b
@@ -55,7 +57,8 @@ _lib = None
 
 def build(force: bool = True) -> str:
     """Compile the brute-force counter with gcc (OpenMP)."""
-    if force or not os.path.exists(_SO):
+    stale = not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC)
+    if force or stale:
         tmp = _SO + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=c99",
                                "-o", tmp, _SRC])
@@ -66,20 +69,19 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_SO):
-            build(force=True)
+        build(force=False)
         lib = ctypes.CDLL(_SO)
         f = lib.oracle_count_pairs
         f.restype = ctypes.c_int
         f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
-                      ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                      ctypes.c_int, ctypes.c_int64, ctypes.c_int, ctypes.c_int64,
                       ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                       ctypes.c_void_p, ctypes.c_int]
         _lib = lib
     return _lib
 
 
-LOS = {"z": 0, "mid": 1}
+LOS = {"z": 0, "mid": 1, "rppi": 2}
 
 _last_threads = 0
 
@@ -89,10 +91,13 @@ def threads_used() -> int:
 
 
 def count_pairs(a: np.ndarray, b: Optional[np.ndarray], edges: Sequence[int], n_mu: int,
-                box_units: int = 0, los: str = "z", threads: int = 0) -> np.ndarray:
+                box_units: int = 0, los: str = "z", threads: int = 0, pi_max: int = 0) -> np.ndarray:
     """Pair counts of catalogue ``a`` with itself (b is None: unordered i<j)
     or with catalogue ``b`` (all i in a, j in b).  a, b: int32 [3, n].
-    Returns uint64 [n_r, n_mu]."""
+    los "rppi": bins in (r_p, pi) along z, edges bin r_p and n_mu uniform
+    pi bins cover [0, pi_max).  Returns uint64 [n_r, n_mu]."""
+    if los == "rppi" and not pi_max >= 1:
+        raise ValueError("the (r_p, pi) binning needs pi_max >= 1")
     global _last_threads
     lib = _load()
     a = np.ascontiguousarray(a, dtype=np.int32)
@@ -103,7 +108,7 @@ def count_pairs(a: np.ndarray, b: Optional[np.ndarray], edges: Sequence[int], n_
     out = np.zeros((n_r, n_mu), dtype=np.uint64)
     _last_threads = lib.oracle_count_pairs(
         a.ctypes.data, a.shape[1], bb.ctypes.data, bb.shape[1], int(auto), int(box_units),
-        LOS[los], n_r, e.ctypes.data, int(n_mu), out.ctypes.data, int(threads))
+        LOS[los], int(pi_max), n_r, e.ctypes.data, int(n_mu), out.ctypes.data, int(threads))
     return out
 
 
@@ -340,6 +345,17 @@ def map_matrix(C: np.ndarray, group, weight, P_out: int) -> np.ndarray:
     """T C T^T: a covariance re-binned with the data vector (Sect. 5.3)."""
     T = linear_map(group, weight, P_out)
     return T @ C @ T.T
+
+
+def projected(xi_rppi: np.ndarray, pi_max: float) -> np.ndarray:
+    """The projected correlation function from xi binned in (r_p, pi) with
+    n_pi uniform pi bins on [0, pi_max): w_p(r_p) = 2 * integral over
+    [0, pi_max) of xi(r_p, pi) dpi, with xi constant within each pi bin,
+    i.e. 2 (pi_max / n_pi) sum_m xi[k, m] (a linear function of xi,
+    Sect. 2.3).  xi_rppi [n_rp, n_pi] -> [n_rp]; pi_max in the unit wanted
+    for w_p."""
+    n_pi = xi_rppi.shape[1]
+    return 2.0 * (pi_max / n_pi) * xi_rppi.sum(axis=1)
 
 
 def linear_construction_general(Ca: np.ndarray, Cb: np.ndarray, m_a: float, m_b: float, M: float):

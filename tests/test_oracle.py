@@ -641,3 +641,107 @@ def test_general_construction_matches_random_theory(oracle_mod):
                   else oracle_mod.random_theory_variance(n, M * n, G_p))
         ratio = np.diag(CM) / theory
         assert abs(ratio.mean() - 1.0) < tol, (M, ratio)
+
+
+# ---------------------------------------------------------------------------
+# (r_p, pi) binning and the projected correlation function (Sect. 2.3)
+# ---------------------------------------------------------------------------
+
+def _rppi_numpy(a, b, edges, n_pi, box, pi_max):
+    """Every pair enumerated with numpy (a separate implementation of the
+    definition): minimal image, r_p^2 = s_x^2 + s_y^2 against squared edges,
+    pi bin = floor(n_pi |s_z| / pi_max) for |s_z| < pi_max."""
+    a = a.astype(np.int64)
+    bb = a if b is None else b.astype(np.int64)
+    s = bb[:, None, :] - a[:, :, None]            # [3, n_a, n_b]
+    if box:
+        s = np.where(s >= box // 2, s - box, np.where(s < -(box // 2), s + box, s))
+    rp2 = s[0] ** 2 + s[1] ** 2
+    az = np.abs(s[2])
+    keep = np.ones(rp2.shape, bool)
+    if b is None:
+        keep = np.triu(keep, 1)
+    e2 = np.asarray(edges, np.int64) ** 2
+    k = np.searchsorted(e2, rp2, side="right") - 1
+    keep &= (k >= 0) & (k < len(edges) - 1) & (az < pi_max)
+    m = (n_pi * az) // pi_max
+    out = np.zeros((len(edges) - 1, n_pi), np.uint64)
+    np.add.at(out, (k[keep], m[keep]), 1)
+    return out
+
+
+@pytest.mark.parametrize("box", [1 << 16, 0])
+def test_rppi_counts_against_numpy_enumeration(oracle_mod, box):
+    lo = 0 if box else 5000
+    hi = box if box else 5000 + (1 << 16)
+    a, b = _rand_pts(51, 300, lo, hi), _rand_pts(52, 250, lo, hi)
+    for edges, n_pi, pi_max in (([0, 2000, 5000, 9000, 16000], 6, 12000), ([700, 800, 3001], 5, 32767),
+                                ([0, 30000], 1, 1)):
+        for bb in (None, b):
+            got = oracle_mod.count_pairs(a, bb, edges, n_pi, box, "rppi", pi_max=pi_max)
+            assert np.array_equal(got, _rppi_numpy(a, bb, edges, n_pi, box, pi_max)), (edges, n_pi, pi_max)
+
+
+def test_rppi_edge_pairs(oracle_mod):
+    """Hand-placed pairs: r_p exactly on an edge belongs to the upper bin;
+    |s_z| = pi_max is dropped and pi_max - 1 kept; |s_z| on a pi edge opens
+    that bin; a pair along the line of sight has r_p = 0; the periodic image
+    across the box is used."""
+    edges, n_pi, pi_max, L = [0, 30, 50, 80], 4, 40, 1000
+    cases = [((0, 0, 0), (30, 0, 0), (1, 0)),       # r_p = 30 on an edge
+             ((0, 0, 0), (18, 24, 0), (1, 0)),      # r_p = 30 (3-4-5)
+             ((0, 0, 0), (29, 0, 0), (0, 0)),
+             ((0, 0, 0), (0, 0, 40), None),         # |s_z| = pi_max
+             ((0, 0, 0), (0, 0, 39), (0, 3)),
+             ((0, 0, 0), (0, 0, 10), (0, 1)),       # |s_z| = pi_max / n_pi
+             ((0, 0, 0), (0, 0, 9), (0, 0)),
+             ((0, 0, 5), (0, 0, 995), (0, 1)),      # image: s_z = -10
+             ((0, 0, 0), (80, 0, 0), None),         # r_p = e_n
+             ((0, 0, 0), (50, 0, -20), (2, 2))]
+    for pi, pj, km in cases:
+        a = np.array(pi, np.int32).reshape(3, 1)
+        b = np.array(pj, np.int32).reshape(3, 1)
+        got = oracle_mod.count_pairs(a, b, edges, n_pi, L, "rppi", pi_max=pi_max)
+        if km is None:
+            assert got.sum() == 0, (pi, pj)
+        else:
+            assert got.sum() == 1 and got[km] == 1, (pi, pj, np.argwhere(got))
+
+
+def test_rppi_union_identity(oracle_mod):
+    L = 1 << 18
+    a, b = _rand_pts(61, 400, 0, L), _rand_pts(62, 350, 0, L)
+    edges = [0, 3000, 7000, 12000]
+    ab = np.concatenate([a, b], axis=1)
+    f = lambda x, y=None: oracle_mod.count_pairs(x, y, edges, 5, L, "rppi", pi_max=9000)
+    assert np.array_equal(f(ab), f(a) + f(b) + f(a, b))
+
+
+def test_rppi_uniform_counts_match_cylinder_volume(oracle_mod):
+    """Uniform points in a periodic box: each (r_p, pi) bin holds the pair
+    count times the volume of its cylindrical shell, 2 pi (e_k+1^2 - e_k^2)
+    (pi_max / n_pi) / L^3, within Poisson noise."""
+    L, n = 1 << 20, 3000
+    a = _rand_pts(71, n, 0, L)
+    edges = np.array([0, 20000, 40000, 60000, 80000])
+    n_pi, pi_max = 4, 80000
+    got = oracle_mod.count_pairs(a, None, edges, n_pi, L, "rppi", pi_max=pi_max).astype(np.float64)
+    area = np.pi * np.diff(edges.astype(np.float64) ** 2)
+    exp = (n * (n - 1) / 2) * (area[:, None] * 2 * (pi_max / n_pi)) / float(L) ** 3 * np.ones((1, n_pi))
+    z = (got - exp) / np.sqrt(exp)
+    assert np.all(np.abs(z) < 5), z
+    assert abs(got.sum() / exp.sum() - 1) < 0.02
+
+
+def test_projected_closed_forms(oracle_mod):
+    """w_p of xi = c is 2 c pi_max; of xi_m = m (bin index) it is
+    2 (pi_max / n) n (n - 1) / 2; it is linear."""
+    n = 8
+    xi = np.full((3, n), 0.25)
+    assert np.allclose(oracle_mod.projected(xi, 40.0), 2 * 0.25 * 40.0)
+    xi = np.tile(np.arange(n, dtype=float), (2, 1))
+    assert np.allclose(oracle_mod.projected(xi, 40.0), 2 * (40.0 / n) * n * (n - 1) / 2)
+    r = np.random.default_rng(3)
+    x, y = r.normal(size=(5, n)), r.normal(size=(5, n))
+    assert np.allclose(oracle_mod.projected(2 * x - y, 7.0),
+                       2 * oracle_mod.projected(x, 7.0) - oracle_mod.projected(y, 7.0))
