@@ -43,6 +43,8 @@ typedef int32_t lc_status;
 
 #define LC_LOS_Z    0       /* plane-parallel, line of sight = z axis (Sect. 4.1) */
 #define LC_LOS_MID  1       /* line of sight = pair midpoint seen from the origin (open geometry) */
+#define LC_LOS_RPPI 2       /* plane-parallel along z, bins in (r_p, pi) instead of (r, mu): the
+                               binning of the projected correlation function (Sect. 2.3) */
 
 #define LC_MAX_BINS 32768   /* n_r * n_mu (the block histogram lives in LDS) */
 #define LC_MAX_NMU  1024
@@ -60,15 +62,24 @@ const char* lc_last_error(void);
  * Every comparison is exact: it equals the integer rule
  *   r_edges[k]^2 <= d^2 < r_edges[k+1]^2 and the largest m < n_mu with
  *   m^2 d^2 <= n_mu^2 s_z^2 (midpoint: m^2 d^2 |l|^2 <= n_mu^2 (s.l)^2, l = x_i + x_j).
+ * LC_LOS_RPPI bins r_p = |(s_x, s_y)| by the r edges
+ *   (r_edges[k]^2 <= s_x^2 + s_y^2 < r_edges[k+1]^2) and pi = |s_z| in n_mu
+ *   uniform bins of [0, pi_max): m = floor(n_mu |s_z| / pi_max); pairs with
+ *   |s_z| >= pi_max are not counted.  The projected correlation function
+ *   w_p(r_p) = 2 sum_m xi(r_p, pi_m) (pi_max / n_mu) is then a linear map of
+ *   the estimate (lc_map_vectors); the multipole part of lc_xi_multipoles'
+ *   output has no meaning for this binning.
  */
 typedef struct {
     int32_t periodic;         /* 1: periodic cube [0, box_units)^3, minimal image; 0: open */
     int32_t box_units;        /* periodic side, even, <= 2^24; ignored when open */
-    int32_t los;              /* LC_LOS_Z or LC_LOS_MID (MID requires periodic = 0) */
+    int32_t los;              /* LC_LOS_Z, LC_LOS_MID (requires periodic = 0) or LC_LOS_RPPI */
     int32_t n_r;              /* >= 1 */
     const int32_t* r_edges;   /* HOST, n_r + 1 strictly increasing values >= 0;
                                  periodic: r_edges[n_r] < box_units / 2; open: < 2^25 */
-    int32_t n_mu;             /* 1 .. LC_MAX_NMU, n_r * n_mu <= LC_MAX_BINS */
+    int32_t n_mu;             /* 1 .. LC_MAX_NMU, n_r * n_mu <= LC_MAX_BINS (LC_LOS_RPPI: pi bins) */
+    int32_t pi_max;           /* LC_LOS_RPPI only: 1 <= pi_max < 2^24 units (periodic: < box_units / 2);
+                                 ignored otherwise */
 } lc_binning;
 
 /*

@@ -180,11 +180,16 @@ class Workload:
     n_r: int
     r_max_mpc: float
     n_mu: int
-    los: str                      # "z" (plane-parallel) or "mid" (midpoint)
+    los: str                      # "z" (plane-parallel), "mid" (midpoint) or "rppi" ((r_p, pi) along z)
+    pi_max_mpc: float = 0.0       # "rppi": line-of-sight extent; n_mu counts its pi bins
 
     @property
     def periodic(self) -> bool:
         return self.geometry == "periodic"
+
+    @property
+    def pi_max_units(self) -> int:
+        return int(round(self.pi_max_mpc * UNITS_PER_MPC))
 
     @property
     def box_units(self) -> int:

@@ -41,6 +41,7 @@ std::string tune_key(int device, const lc_binning* b, const int64_t* off, int32_
     mix(h, uint64_t(b->los));
     mix(h, uint64_t(b->n_r));
     mix(h, uint64_t(b->n_mu));
+    mix(h, uint64_t(b->los == LC_LOS_RPPI ? b->pi_max : 0));
     for (int k = 0; k <= b->n_r; k++) mix(h, uint64_t(b->r_edges[k]));
     mix(h, uint64_t(n_cat));
     for (int32_t c = 0; c <= n_cat; c++) mix(h, uint64_t(off[c]));
@@ -112,7 +113,7 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
     const int32_t ns = std::min(n_tasks, sample_tasks);
     for (int32_t i = 0; i < ns; i++) sample.push_back(tasks[int64_t(i) * n_tasks / ns]);
 
-    const int64_t rmax = b->r_edges[b->n_r];
+    const int64_t rmax = mesh_reach(b);
     const bool mid = b->los == LC_LOS_MID;
     const int nbins = b->n_r * b->n_mu;
     uint64_t* counts = nullptr;

@@ -22,15 +22,17 @@ lc_status check_binning(const lc_binning* b) {
                     LC_MAX_BINS);
     if (b->periodic != 0 && b->periodic != 1)
         return fail(LC_ERR_INVALID, "periodic = %d, must be 0 or 1", b->periodic);
-    if (b->los != LC_LOS_Z && b->los != LC_LOS_MID)
-        return fail(LC_ERR_INVALID, "los = %d, must be LC_LOS_Z or LC_LOS_MID", b->los);
+    if (b->los != LC_LOS_Z && b->los != LC_LOS_MID && b->los != LC_LOS_RPPI)
+        return fail(LC_ERR_INVALID, "los = %d, must be LC_LOS_Z, LC_LOS_MID or LC_LOS_RPPI", b->los);
     if (b->los == LC_LOS_MID && b->periodic)
         return fail(LC_ERR_INVALID, "the midpoint line of sight needs open geometry");
+    if (b->los == LC_LOS_RPPI && (b->pi_max < 1 || b->pi_max >= kLimit24))
+        return fail(LC_ERR_INVALID, "pi_max = %d, must be in [1, 2^24) for LC_LOS_RPPI", b->pi_max);
     if (b->r_edges[0] < 0) return fail(LC_ERR_INVALID, "r_edges[0] = %d < 0", b->r_edges[0]);
     for (int k = 0; k < b->n_r; k++)
         if (b->r_edges[k + 1] <= b->r_edges[k])
             return fail(LC_ERR_INVALID, "r_edges not strictly increasing at %d", k);
-    const int64_t rmax = b->r_edges[b->n_r];
+    const int64_t rmax = mesh_reach(b);
     if (b->periodic) {
         if (b->box_units < 2 || b->box_units > kLimit24 || (b->box_units & 1))
             return fail(LC_ERR_INVALID, "box_units = %d must be even and in [2, 2^24]", b->box_units);
@@ -43,23 +45,33 @@ lc_status check_binning(const lc_binning* b) {
     return LC_OK;
 }
 
-int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out) {
+int64_t mesh_reach(const lc_binning* b) {
+    const int64_t r = b->r_edges[b->n_r];
+    return b->los == LC_LOS_RPPI ? std::max<int64_t>(r, b->pi_max) : r;
+}
+
+int build_stencil(const GridGeom& g, int64_t r_max, int64_t pi_max, std::vector<int4>& out) {
     // Two cells whose indices differ by d along an axis are more than
-    // (|d| - 1) * w apart on it (w = ext / n): an offset with
+    // (|d| - 1) * w apart on it (w = ext / n).  Isotropic: an offset with
     // sum max(|d|-1, 0)^2 w^2 >= r_max^2 cannot hold a pair with r < r_max.
-    // Decided exactly: multiply through by (n_x n_y n_z)^2 in 128-bit integers.
+    // (r_p, pi): the sum runs over x and y only (against r_max, the r_p
+    // bound), and max(|d_z|-1, 0) w_z >= pi_max rules out |s_z| < pi_max.
+    // Decided exactly: multiply through by the n_a^2 in 128-bit integers.
     typedef unsigned __int128 u128;
+    const bool rppi = pi_max > 0;
+    const int nax = rppi ? 2 : 3;  // axes in the squared-distance sum
     int k[3];
-    u128 wt[3];  // ext_a^2 * prod_{b != a} n_b^2
+    u128 wt[3];  // ext_a^2 * prod_{b != a, b < nax} n_b^2
     u128 rhs = u128(uint64_t(r_max)) * uint64_t(r_max);
+    for (int a = 0; a < nax; a++) rhs *= u128(uint64_t(g.n[a])) * uint64_t(g.n[a]);
     for (int a = 0; a < 3; a++) {
-        rhs *= u128(uint64_t(g.n[a])) * uint64_t(g.n[a]);
         wt[a] = u128(uint64_t(g.ext[a])) * uint64_t(g.ext[a]);
-        for (int b = 0; b < 3; b++)
+        for (int b = 0; b < nax; b++)
             if (b != a) wt[a] *= u128(uint64_t(g.n[b])) * uint64_t(g.n[b]);
-        // smallest |d| with (|d| - 1) * w >= r_max, capped: one full turn of a
+        // smallest |d| with (|d| - 1) * w >= reach, capped: one full turn of a
         // periodic grid (or the whole open grid) reaches every cell
-        int64_t kk = (r_max * g.n[a]) / g.ext[a] + 1;
+        const int64_t reach = (rppi && a == 2) ? pi_max : r_max;
+        int64_t kk = (reach * g.n[a]) / g.ext[a] + 1;
         k[a] = int(std::min<int64_t>(kk, g.n[a]));
     }
     std::vector<int4> pos, neg;
@@ -69,11 +81,16 @@ int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out) {
                 if (!dx && !dy && !dz) continue;
                 const int d[3] = {dx, dy, dz};
                 u128 s = 0;
-                for (int a = 0; a < 3; a++) {
+                for (int a = 0; a < nax; a++) {
                     const uint64_t m = uint64_t(std::max(std::abs(d[a]) - 1, 0));
                     s += u128(m * m) * wt[a];
                 }
                 if (s >= rhs) continue;
+                if (rppi) {
+                    // (|d_z| - 1) ext_z / n_z >= pi_max, exactly
+                    const int64_t mz = std::max(std::abs(dz) - 1, 0);
+                    if (mz * g.ext[2] >= pi_max * int64_t(g.n[2])) continue;
+                }
                 const bool positive = dz > 0 || (dz == 0 && (dy > 0 || (dy == 0 && dx > 0)));
                 (positive ? pos : neg).push_back(make_int4(dx, dy, dz, 0));
             }
@@ -319,7 +336,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
     hipStream_t s = (hipStream_t)stream;
-    const int64_t rmax = b->r_edges[b->n_r];
+    const int64_t rmax = mesh_reach(b);
 
     GridGeom g{};
     g.periodic = b->periodic;

@@ -122,11 +122,15 @@ namespace lc {
 // Validates a binning (see lc.h); LC_OK or LC_ERR_INVALID / LC_ERR_RANGE.
 lc_status check_binning(const lc_binning* b);
 
-// Number of stencil offsets and the list itself for a mesh and r_max.
-// Order: [0] = (0,0,0); then the lexicographically positive half; then the
-// negative half.  Offsets whose cells cannot hold a pair closer than r_max
-// are pruned.  Returns n_half (self + positive half).
-int build_stencil(const GridGeom& g, int64_t r_max, std::vector<int4>& out);
+// Number of stencil offsets and the list itself for a mesh and r_max
+// (pi_max > 0: the (r_p, pi) binning, r_max bounding r_p in x and y and
+// pi_max bounding |s_z|).  Order: [0] = (0,0,0); then the lexicographically
+// positive half; then the negative half.  Offsets whose cells cannot hold a
+// counted pair are pruned.  Returns n_half (self + positive half).
+int build_stencil(const GridGeom& g, int64_t r_max, int64_t pi_max, std::vector<int4>& out);
+// Largest separation along any axis that a counted pair can have: r_max,
+// or for the (r_p, pi) binning the larger of the r_p bound and pi_max.
+int64_t mesh_reach(const lc_binning* b);
 
 // Drop the cached pair-count graphs and autotuning results.
 void release_graphs();

@@ -65,6 +65,7 @@ struct PcParams {
     // estimates shifted down by their margins and the single-compare bounds
     // on their fractions (see bin_fast)
     float r_shift, ok_r, mu_shift, ok_m;
+    float pimax_f;              // (r_p, pi) binning: |s_z| bound (an exact integer)
     uint32_t wave_limit;        // candidate tests a wave may register between flushes
     uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
@@ -79,6 +80,7 @@ struct ExactTab {
     int32_t n_r, n_mu;
     int32_t discard;        // histogram slot of dropped pairs (= n_r n_mu)
     int32_t pad;
+    int64_t pi_max;         // (r_p, pi) binning: |s_z| bound
     int64_t e2[1];          // [n_r + 1] squared edges (flexible tail)
 };
 
@@ -142,6 +144,34 @@ __device__ __forceinline__ int exact_bin_z(double x, double y, double z, int k_e
         while (m < n_mu - 1 && prod_le(double(m + 1) * double(m + 1), D2, nm2, z2)) ++m;
     }
     return k * n_mu + m;
+}
+
+// Integer rule for the (r_p, pi) binning, in float64 (exact: the components
+// are integers below 2^25): r_p^2 = s_x^2 + s_y^2 against the squared edges,
+// pi bin = floor(n_pi |s_z| / pi_max) for |s_z| < pi_max.
+template <bool UNIFORM>
+__device__ __forceinline__ int exact_bin_rppi(double x, double y, double z, int k_est,
+                                              const ExactTab* __restrict__ xt) {
+    const double RP2 = fma(x, x, y * y);
+    const int64_t az = int64_t(fabs(z));
+    if (RP2 >= double(xt->emax2) || RP2 < double(xt->emin2) || az >= xt->pi_max) return xt->discard;
+    const int n_r = xt->n_r, n_mu = xt->n_mu;
+    int k;
+    if (UNIFORM) {
+        const double e0 = double(xt->e0), de = double(xt->de);
+        k = min(max(k_est, 0), n_r - 1);
+        while (k > 0 && RP2 < (e0 + k * de) * (e0 + k * de)) --k;
+        while (k < n_r - 1 && RP2 >= (e0 + (k + 1) * de) * (e0 + (k + 1) * de)) ++k;
+    } else {
+        int lo = 0, hi = n_r;  // e2[lo] <= RP2 < e2[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (double(xt->e2[mid]) <= RP2) lo = mid;
+            else hi = mid;
+        }
+        k = lo;
+    }
+    return k * n_mu + int((int64_t(n_mu) * az) / xt->pi_max);
 }
 
 // Integer rule (the binning of Sect. 4.3 with exact comparisons): the bin of
@@ -221,6 +251,11 @@ __device__ __forceinline__ int bin_fast(const float4 e, const int* __restrict__ 
     if (LOS == 0) {
         d2f = e.w;
         u = fmaf(fabsf(e.z) * __builtin_amdgcn_rsqf(d2f), p.nmuf, -p.mu_shift);
+    } else if (LOS == 2) {
+        // (r_p, pi): e.w = r_p^2; |s_z| is an exact integer and nmuf holds
+        // n_pi / pi_max, so the pi estimate is one fma
+        d2f = e.w;
+        u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
         // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
         // exact in float64 (< 2^53)
@@ -261,6 +296,11 @@ __device__ __forceinline__ int exact_entry(const float4 e, const int* __restrict
     const double x = e.x, y = e.y, z = e.z;
     const double d2 = fma(x, x, fma(y, y, z * z));
     const double r = sqrt(d2);
+    if (LOS == 2) {
+        const double rp = sqrt(fma(x, x, y * y));
+        const int kp_est = UNIFORM ? int((rp - double(xt->e0)) / double(xt->de)) : 0;
+        return exact_bin_rppi<UNIFORM>(x, y, z, kp_est, xt);
+    }
     const int k_est = UNIFORM ? int((r - double(xt->e0)) / double(xt->de)) : 0;
     if (LOS == 0) {
         const int m_est = d2 > 0.0 ? int(fabs(z) / r * double(xt->n_mu)) : 0;
@@ -373,23 +413,30 @@ struct Cand {
 
 // Separation and float32 squared distance of one candidate; accepted when
 // d2 < e_max^2 (1 + 2^-20), which holds for every pair with r < e_max since
-// the float32 sum of three exact squares is within 3 * 2^-24 of d2.
-template <bool HAS_EMIN>
+// the float32 sum of three exact squares is within 3 * 2^-24 of d2.  The
+// (r_p, pi) binning (LOS 2) tests r_p^2 = s_x^2 + s_y^2 the same way and
+// |s_z| < pi_max exactly (both are integers below 2^24).
+template <int LOS, bool HAS_EMIN>
 __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi, float yi, float zi,
                                           const PcParams& p) {
     Cand c;
     c.dx = xj - xi;
     c.dy = yj - yi;
     c.dz = zj - zi;
-    c.d2 = fmaf(c.dx, c.dx, fmaf(c.dy, c.dy, c.dz * c.dz));
-    c.acc = c.d2 < p.emax2_hi;
+    if (LOS == 2) {
+        c.d2 = fmaf(c.dx, c.dx, c.dy * c.dy);
+        c.acc = (c.d2 < p.emax2_hi) && (fabsf(c.dz) < p.pimax_f);
+    } else {
+        c.d2 = fmaf(c.dx, c.dx, fmaf(c.dy, c.dy, c.dz * c.dz));
+        c.acc = c.d2 < p.emax2_hi;
+    }
     if (HAS_EMIN) c.acc = c.acc && (c.d2 >= p.emin2_lo);
     return c;
 }
 
 // Append the accepted lanes of one candidate to the queue (length qt, kept
-// wave-uniform); bin 64 of them as soon as 64 are queued.  w4: d2
-// (plane-parallel) or the i index within the chunk (midpoint).
+// wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the i index
+// within the chunk (midpoint); the other modes queue d2 (r_p^2).
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
                                          uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
@@ -402,7 +449,7 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
                 __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
             const uint32_t base = w.qbyte + qt * 16u;
             *reinterpret_cast<float4*>(smem_base() + base + rank * 16u) =
-                make_float4(c.dx, c.dy, c.dz, LOS == 0 ? c.d2 : w4);
+                make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
         if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0>(w, lane, 64, qt, p, xt);
@@ -433,7 +480,7 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
     Cand c[4];
 #pragma unroll
     for (int u = 0; u < 4; u++) {
-        c[u] = test_pair<HAS_EMIN>(xj, yj, zj, a[3 * u], a[3 * u + 1], a[3 * u + 2], p);
+        c[u] = test_pair<LOS, HAS_EMIN>(xj, yj, zj, a[3 * u], a[3 * u + 1], a[3 * u + 2], p);
         if (SELF) c[u].acc = c[u].acc && (jrel > k + u);
     }
     // ballots before any branch keep the four distance chains together; one
@@ -443,6 +490,7 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
 #pragma unroll
     for (int u = 0; u < 4; u++) {
         unsigned long long b = __builtin_amdgcn_ballot_w64(c[u].d2 < p.emax2_hi);
+        if (LOS == 2) b &= __builtin_amdgcn_ballot_w64(fabsf(c[u].dz) < p.pimax_f);
         if (HAS_EMIN) b &= __builtin_amdgcn_ballot_w64(c[u].d2 >= p.emin2_lo);
         if (SELF) b &= __builtin_amdgcn_ballot_w64(jrel > k + u);
         if (TAIL && k + u >= n_i) b = 0;
@@ -664,8 +712,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         const float gx = fmaxf(0.0f, fmaxf(lx - bhx, blx - hx));
                         const float gy = fmaxf(0.0f, fmaxf(ly - bhy, bly - hy));
                         const float gz = fmaxf(0.0f, fmaxf(lz - bhz, blz - hz));
-                        const float g2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
-                        runs = __builtin_amdgcn_ballot_w64((lane < nsub) && (g2 < p.emax2_hi));
+                        bool keep;
+                        if (LOS == 2) {
+                            // (r_p, pi): transverse gap against the r_p bound,
+                            // line-of-sight gap against pi_max
+                            keep = (fmaf(gx, gx, gy * gy) < p.emax2_hi) && (gz < p.pimax_f);
+                        } else {
+                            keep = fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < p.emax2_hi;
+                        }
+                        runs = __builtin_amdgcn_ballot_w64((lane < nsub) && keep);
                     }
                     while (self || runs) {
                         int64_t jb, je;
@@ -727,11 +782,13 @@ typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_
                          const int32_t*, unsigned long long*, unsigned long long*, unsigned*, PcParams);
 
 static PcKernel pick_kernel(int los, bool uniform, bool has_emin) {
-    static const PcKernel tab[2][2][2] = {
+    static const PcKernel tab[3][2][2] = {
         {{k_pair_count<0, false, false>, k_pair_count<0, false, true>},
          {k_pair_count<0, true, false>, k_pair_count<0, true, true>}},
         {{k_pair_count<1, false, false>, k_pair_count<1, false, true>},
          {k_pair_count<1, true, false>, k_pair_count<1, true, true>}},
+        {{k_pair_count<2, false, false>, k_pair_count<2, false, true>},
+         {k_pair_count<2, true, false>, k_pair_count<2, true, true>}},
     };
     return tab[los][uniform ? 1 : 0][has_emin ? 1 : 0];
 }
@@ -790,7 +847,8 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     for (int a = 0; a < 3; a++) p.wf[a] = float(double(g.ext[a]) / (double(g.n[a]) * g.sub));
     std::vector<int4> sten;
     const int64_t rmax = b->r_edges[n_r];
-    p.nhalf = build_stencil(g, rmax, sten);
+    const bool rppi = b->los == LC_LOS_RPPI;
+    p.nhalf = build_stencil(g, rmax, rppi ? int64_t(b->pi_max) : 0, sten);
     p.nfull = int(sten.size());
     // relative coordinates and the cell-origin offsets used in float32 must
     // stay below 2^24 in magnitude (exact integers)
@@ -836,13 +894,17 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.emax2_hi = f32_up(double(emax2) * (1.0 + std::ldexp(1.0, -20)));
     p.emin2_lo = f32_down(double(emin2) * (1.0 - std::ldexp(1.0, -20)));
     p.inv_drf = float(1.0 / double(de));
-    p.nmuf = float(n_mu);
+    // (r_p, pi): the pi estimate is |s_z| n_pi / pi_max
+    p.nmuf = rppi ? float(double(n_mu) / double(b->pi_max)) : float(n_mu);
+    p.pimax_f = rppi ? float(b->pi_max) : 0.0f;
     // Float32 error bounds in units of u = 2^-24 (relative error per rounding;
     // v_rsq_f32 is within 1 ulp = 2u):
     //   d2 (float32 sum of exact squares): 3u
     //   mu estimate |s_z| rsq(d2) n_mu - eps_m: 1.5u (from d2) + 2u + a product
     //     and an fma 2u -> 5.5u n_mu absolute; midpoint: p and q conversions,
-    //     rsq(q), one more product -> 10u n_mu
+    //     rsq(q), one more product -> 10u n_mu; (r_p, pi): the exact |s_z|
+    //     times a rounded n_pi / pi_max in one fma -> 2u n_pi (r_p^2, a sum of
+    //     two exact squares, is within the 3u of d2)
     //   r estimate d2 rsq(d2): 1.5u + 2u + 1u = 4.5u of r; t = r/de - (e0/de +
     //     eps_r) by one fma with rounded 1/de and a rounded shift ->
     //     u (5.5 r_max + e0)/de + u (n_r + 1)
@@ -865,7 +927,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     // takes the integer rule
     if (mode & LC_FORCE_EXACT) p.ok_r = -1.0f;
     const bool has_emin = e0 > 0;
-    pl.kern = pick_kernel(mid ? 1 : 0, uniform, has_emin);
+    pl.kern = pick_kernel(mid ? 1 : rppi ? 2 : 0, uniform, has_emin);
     pl.mode = mode;
     pl.n_tasks = n_tasks;
 
@@ -975,6 +1037,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
         head.n_r = n_r;
         head.n_mu = n_mu;
         head.discard = p.nbins;
+        head.pi_max = rppi ? int64_t(b->pi_max) : 0;
         std::memcpy(xtab.data(), &head, offsetof(ExactTab, e2));
         std::memcpy(xtab.data() + offsetof(ExactTab, e2), e2.data(), sizeof(int64_t) * e2.size());
     }

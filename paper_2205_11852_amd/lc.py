@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblc.so")
 
 LC_OK, LC_ERR_INVALID, LC_ERR_RANGE, LC_ERR_OVERFLOW, LC_ERR_HIP, LC_ERR_NOMEM = 0, -1, -2, -3, -4, -5
-LC_LOS_Z, LC_LOS_MID = 0, 1
+LC_LOS_Z, LC_LOS_MID, LC_LOS_RPPI = 0, 1, 2
 LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
 LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED = 0, 1, 2
 LC_MAX_BINS, LC_MAX_NMU = 32768, 1024
@@ -47,7 +47,7 @@ class LcError(RuntimeError):
 class lc_binning(ctypes.Structure):
     _fields_ = [("periodic", ctypes.c_int32), ("box_units", ctypes.c_int32), ("los", ctypes.c_int32),
                 ("n_r", ctypes.c_int32), ("r_edges", ctypes.POINTER(ctypes.c_int32)),
-                ("n_mu", ctypes.c_int32)]
+                ("n_mu", ctypes.c_int32), ("pi_max", ctypes.c_int32)]
 
 
 class lc_task(ctypes.Structure):
@@ -200,12 +200,16 @@ class Binning:
     """Owns the host edge array that lc_binning points at."""
 
     def __init__(self, r_edges: Sequence[int], n_mu: int, periodic: bool, box_units: int = 0,
-                 los: int = LC_LOS_Z):
+                 los: int = LC_LOS_Z, pi_max: int = 0):
+        """los = LC_LOS_RPPI: r_edges bin r_p and n_mu counts the pi bins of
+        [0, pi_max)."""
         self.edges = np.ascontiguousarray(np.asarray(r_edges, dtype=np.int32))
         self.n_r = len(self.edges) - 1
         self.n_mu = int(n_mu)
+        self.pi_max = int(pi_max)
         self.c = lc_binning(int(bool(periodic)), int(box_units), int(los), int(self.n_r),
-                            self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_mu))
+                            self.edges.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(n_mu),
+                            int(pi_max))
 
     @property
     def P(self) -> int:
@@ -213,8 +217,8 @@ class Binning:
 
     @classmethod
     def from_workload(cls, wl) -> "Binning":
-        return cls(wl.r_edges_units, wl.n_mu, wl.periodic, wl.box_units,
-                   LC_LOS_MID if wl.los == "mid" else LC_LOS_Z)
+        los = {"z": LC_LOS_Z, "mid": LC_LOS_MID, "rppi": LC_LOS_RPPI}[wl.los]
+        return cls(wl.r_edges_units, wl.n_mu, wl.periodic, wl.box_units, los, wl.pi_max_units)
 
 
 def tasks_array(tasks) -> np.ndarray:

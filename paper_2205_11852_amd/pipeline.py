@@ -80,6 +80,20 @@ def multipole_map(n_r: int, n_mu: int, w: int = 1, r_lo: int = 0, r_hi: Optional
     return group, weight, len(ells) * n_out
 
 
+def projected_map(n_rp: int, n_pi: int, pi_max: float) -> Tuple[np.ndarray, np.ndarray, int]:
+    """Map (group, weight, P_out) from the data vector of a (r_p, pi)
+    binning (LC_LOS_RPPI: xi(r_p, pi) r_p-major, then the unused multipole
+    part) to the projected correlation function
+    w_p(r_p) = 2 sum_m xi(r_p, pi_m) (pi_max / n_pi), in the unit of pi_max."""
+    P = n_rp * n_pi + 3 * n_rp
+    group = np.full(P, -1, dtype=np.int32)
+    weight = np.zeros(P)
+    nb = n_rp * n_pi
+    group[:nb] = np.repeat(np.arange(n_rp, dtype=np.int32), n_pi)
+    weight[:nb] = 2.0 * pi_max / n_pi
+    return group, weight, n_rp
+
+
 def block_rebin_map(n_blocks: int, n: int, w: int) -> Tuple[np.ndarray, np.ndarray, int]:
     """Map (group, weight, P_out) that averages w adjacent elements within
     each of n_blocks consecutive blocks of n (e.g. the r bins of each
@@ -275,7 +289,8 @@ class Pipeline:
         lc.lc_rebin_counts(self.counts, len(self.tasks), b.n_r, b.n_mu, w_r, w_mu, out)
         e = b.edges
         edges = [int(e[min(k * w_r, b.n_r)]) for k in range(n_r2 + 1)]
-        return out, lc.Binning(edges, b.n_mu // w_mu, bool(b.c.periodic), int(b.c.box_units), int(b.c.los))
+        return out, lc.Binning(edges, b.n_mu // w_mu, bool(b.c.periodic), int(b.c.box_units), int(b.c.los),
+                               b.pi_max)
 
     def xi_of(self, counts, binning) -> "object":
         """lc_xi_multipoles of other counts of the same tasks (e.g. co-added)."""

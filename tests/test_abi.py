@@ -67,6 +67,10 @@ def _build_status(L, b, n_total=4, offsets=(0, 4), out=True, xyz=0x1000):
     (dict(los=lc.LC_LOS_MID), lc.LC_ERR_INVALID),            # midpoint needs open geometry
     (dict(los=7, periodic=False), lc.LC_ERR_INVALID),
     (dict(periodic=False, r_edges=[0, 1 << 25]), lc.LC_ERR_RANGE),
+    (dict(los=lc.LC_LOS_RPPI), lc.LC_ERR_INVALID),                          # pi_max missing
+    (dict(los=lc.LC_LOS_RPPI, pi_max=1 << 24, periodic=False), lc.LC_ERR_INVALID),
+    (dict(los=lc.LC_LOS_RPPI, pi_max=500), lc.LC_ERR_RANGE),                # pi_max >= box/2
+    (dict(los=3), lc.LC_ERR_INVALID),
 ])
 def test_build_cells_rejects_bad_binning(L, kw, code):
     assert _build_status(L, _binning(**kw)) == code
