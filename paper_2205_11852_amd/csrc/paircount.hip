@@ -39,6 +39,7 @@
 namespace lc {
 
 constexpr int kQ = 128;     // entries of the per-wave compaction queue
+static_assert(kQ >= 127, "a drain reads queue slots up to 63 + 63");
 constexpr int kX = 128;     // entries of the per-wave queue of pairs for the integer rule
 constexpr int kXcd = 8;     // queues (one per XCD)
 
@@ -66,6 +67,7 @@ struct PcParams {
     // on their fractions (see bin_fast)
     float r_shift, ok_r, mu_shift, ok_m;
     float pimax_f;              // (r_p, pi) binning: |s_z| bound (an exact integer)
+    uint32_t nmu4;              // 4 n_mu: bytes per r row of the histogram
     uint32_t wave_limit;        // candidate tests a wave may register between flushes
     uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
@@ -233,59 +235,63 @@ __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Histogram slot of one queued pair from its float32 estimates.  They are
-// kept only when farther than eps from every edge (ok); otherwise the pair
-// takes the integer rule later.  d2 = 0 (and q = 0) give NaN or clamped
-// estimates that fail the test, so every value stays finite.  (eps_r >= 1
-// sends every pair to the integer rule.)
+// LDS byte address (in the block histogram at offset 0) of one queued pair's
+// bin from its float32 estimates, and the fractions fm (mu) and fr (r) that
+// decide whether the estimates are kept: only when fm < ok_m and fr < ok_r,
+// i.e. farther than eps from every edge; otherwise the pair takes the
+// integer rule later.  d2 = 0 (and q = 0) give NaN or clamped estimates that
+// fail the test, so every value stays finite.  (A bound below 0 sends every
+// pair to the integer rule.)
 template <int LOS, bool UNIFORM, bool HAS_E0>
-__device__ __forceinline__ int bin_fast(const float4 e, const int* __restrict__ itab, const PcParams& p,
-                                        bool& ok) {
+__device__ __forceinline__ uint32_t bin_fast(const float4 e, const int* __restrict__ itab, const PcParams& p,
+                                             float& fm, float& fr) {
     // Each estimate is shifted down by its margin eps inside the FMA that
     // forms it, x' = x - eps.  Then fract(x') < 1 - 2 eps (one compare)
     // holds only when x lies in (floor(x') + eps', floor(x') + 1 - eps') with
     // eps' = eps minus the estimate's own error, i.e. strictly inside the
     // bin floor(x').  A shifted value below 0 (x within eps of 0) has a
-    // fraction near 1 and fails, and so does NaN.
-    float d2f, u;
+    // fraction near 1 and fails, and so does NaN.  The scale constants are
+    // folded into rsq(d2) first, so each FMA reads one scalar operand.
+    float d2f, u, rs;
     if (LOS == 0) {
         d2f = e.w;
-        u = fmaf(fabsf(e.z) * __builtin_amdgcn_rsqf(d2f), p.nmuf, -p.mu_shift);
+        rs = __builtin_amdgcn_rsqf(d2f);
+        u = fmaf(fabsf(e.z), rs * p.nmuf, -p.mu_shift);
     } else if (LOS == 2) {
         // (r_p, pi): e.w = r_p^2; |s_z| is an exact integer and nmuf holds
         // n_pi / pi_max, so the pi estimate is one fma
         d2f = e.w;
+        rs = __builtin_amdgcn_rsqf(d2f);
         u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
         // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
-        // exact in float64 (< 2^53)
-        const int il = __float_as_int(e.w);
+        // exact in float64 (< 2^53).  The i index is clamped so that a lane
+        // past the drained entries (masked by the caller) reads inside the table.
+        const int il = min(max(__float_as_int(e.w), 0), 63);
         const double lx = 2.0 * double(itab[3 * il]) + double(e.x);
         const double ly = 2.0 * double(itab[3 * il + 1]) + double(e.y);
         const double lz = 2.0 * double(itab[3 * il + 2]) + double(e.z);
         const double P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
         const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
         d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
-        u = fmaf(fabsf(float(P)) * __builtin_amdgcn_rsqf(d2f) * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)),
-                 p.nmuf, -p.mu_shift);
+        rs = __builtin_amdgcn_rsqf(d2f);
+        u = fmaf(fabsf(float(P)) * rs * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)), p.nmuf, -p.mu_shift);
     }
     // |mu| n_mu <= n_mu exactly; an estimate within eps_m of n_mu (mu near 1)
-    // fails the test below, so m < n_mu whenever ok
-    const int m = int(u);
-    ok = __builtin_amdgcn_fractf(u) < p.ok_m;
-    int k = 0;
+    // fails the test, so m < n_mu whenever the pair is kept
+    const uint32_t m = uint32_t(int(u));
+    fm = __builtin_amdgcn_fractf(u);
+    uint32_t k = 0;
+    fr = 2.0f;  // non-uniform edges: fails every bound, the integer rule bins
     if (UNIFORM) {
         // eps_r also covers phase A's acceptance margin, so a pair outside
-        // [e_0, e_n) never passes this test with k outside [0, n_r)
-        const float r = d2f * __builtin_amdgcn_rsqf(d2f);
-        const float t = fmaf(r, p.inv_drf, -p.r_shift);
-        k = int(t);
-        ok = ok & (__builtin_amdgcn_fractf(t) < p.ok_r);
-    } else {
-        ok = false;  // non-uniform edges: every pair takes the integer rule
+        // [e_0, e_n) never passes the test with k outside [0, n_r)
+        const float t = fmaf(d2f, rs * p.inv_drf, -p.r_shift);
+        k = uint32_t(int(t));
+        fr = __builtin_amdgcn_fractf(t);
     }
-    // 24-bit multiply: k < n_r and n_mu are far below 2^24
-    return int(__umul24(uint32_t(k), uint32_t(p.n_mu))) + m;
+    // 24-bit multiply-add: k < n_r and 4 n_mu are far below 2^24
+    return __umul24(k, p.nmu4) + (m << 2);
 }
 
 // Histogram slot of one queued pair by the integer rule (discard slot when it
@@ -336,23 +342,34 @@ __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t
 // Bin the last n (<= 64) of the qt queued pairs, one per lane (the queue is
 // an unordered bag, so taking from its end leaves the rest in place).  Pairs
 // the estimates cannot decide move to the integer-rule queue, which is binned
-// 64 at a time.  Returns the new queue length.
+// 64 at a time.  Returns the new queue length.  Every lane reads a slot:
+// first + lane stays inside the queue (a full drain starts at most 63
+// entries in, since the queue held fewer than 64 before the last append of
+// at most 64; a partial drain starts at 0), and lanes past n are masked.
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = qt - n;
-    float4 e = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    bool ok = true;
-    if (uint32_t(lane) < n) {
-        e = w.qa[first + lane];
-        const int bin = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.itab, p, ok);
-        if (ok) __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    }
-    const unsigned long long xb = __builtin_amdgcn_ballot_w64(!ok);
+    const float4 e = w.qa[first + lane];
+    float fm, fr;
+    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.itab, p, fm, fr);
+    const bool live = uint32_t(lane) < n;
+    const unsigned long long live_mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
+    // The lanes the estimates do not decide, from the two compares' lane
+    // masks combined on the scalar unit (predicate 4 = ordered less-than, so
+    // NaN fails).  The compiler shares these compares with the ones that
+    // mask the histogram add; a ballot of the combined bool would copy the
+    // mask through a vector register first.
+    const unsigned long long xb =
+        live_mask & ~(__builtin_amdgcn_fcmpf(fm, p.ok_m, 4) & __builtin_amdgcn_fcmpf(fr, p.ok_r, 4));
+    const bool ok = (fm < p.ok_m) && (fr < p.ok_r);
+    if (ok && live)
+        __hip_atomic_fetch_add(reinterpret_cast<unsigned*>(reinterpret_cast<unsigned char*>(w.hist) + addr), 1u,
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (xb) {
         uint32_t xn = __builtin_amdgcn_readfirstlane(w.xn);
-        if (!ok) {
+        if (live && !ok) {
             const uint32_t rank =
                 __builtin_amdgcn_mbcnt_hi(uint32_t(xb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(xb), 0u));
             w.xa[xn + rank] = e;
@@ -873,6 +890,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.n_r = n_r;
     p.n_mu = n_mu;
     p.nbins = n_r * n_mu;
+    p.nmu4 = uint32_t(4 * n_mu);
     p.hist_stride = (p.nbins + 1 + 3) & ~3;  // + the discard slot
     const bool mid = b->los == LC_LOS_MID;
     const int max_chunk = mid ? 64 : 256;  // midpoint: the i table holds 64 points
