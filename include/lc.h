@@ -380,9 +380,10 @@ typedef struct {
  * does, through the number of candidate tests and the cost of gathering
  * neighbour cells.  Candidates: cell sides r_max / k (k = 1, 1.5, 2, 3, 4) and
  * the default, each with sub-cell splits 1, 2 and 4; then chunks of i points
- * for the best mesh.  (Waves per block keep the library default: a sample
- * of the tasks does not predict that choice for the whole batch.)  Each is
- * timed with HIP events over `sample_tasks` tasks
+ * for the best mesh.  The library default is timed first, and a candidate
+ * replaces the incumbent only when it is more than 2% faster on the sample
+ * (waves per block keep the default: a sample of the tasks predicts small
+ * differences poorly for the whole batch).  Each is timed with HIP events over `sample_tasks` tasks
  * spread evenly over the list (one untimed launch, then two timed).
  *   xyz, n_total, cat_offsets, n_cat, b   as for lc_build_cells.
  *   tasks     HOST [n_tasks], as for lc_pair_count_batch.
