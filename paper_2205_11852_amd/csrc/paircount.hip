@@ -1,6 +1,7 @@
 // Pair counting in (r, mu) bins for many catalogue pairs at once: the DD,
 // DR_i and RR_i counts of the split Landy-Szalay estimator (Sect. 2.1),
-// binned as in Sect. 4.3.
+// binned as in Sect. 4.3 (or in (r_p, pi) for the projected correlation
+// function, Sect. 2.3).
 //
 // Data: every catalogue is sorted into a shared chaining mesh; points are
 // stored as float32 (x, y, z) relative to their cell's integer origin, so
@@ -10,10 +11,12 @@
 // Work decomposition: a work item is (task, run of consecutive cells of
 // catalogue a).  Items form eight queues, one per XCD (workgroup w runs on
 // XCD w mod 8), each holding a contiguous, cost-balanced range of tasks so
-// that the waves sharing an XCD's L2 share catalogues; a wave whose queue is
-// empty moves on to the next queue.  For every cell a wave takes up to 64
-// points of catalogue a (one per lane) and streams the points of each
-// neighbour cell of catalogue b through wave-uniform scalar loads.
+// that the blocks sharing an XCD's L2 share catalogues; a block whose queue
+// is empty moves on to the next queue.  A block takes one item at a time and
+// its waves share the item's stencil offsets.  For each chunk of i points
+// (up to a whole cell of catalogue a, read through wave-uniform scalar
+// loads), a wave gathers the points of the kept neighbour sub-cells of
+// catalogue b into blocks of 64, one per lane.
 //
 // Phase A (every candidate, all lanes): separation and a float32 squared
 // distance, accepted against r_max with a margin larger than its rounding
@@ -21,11 +24,12 @@
 // (ballot + mbcnt), so phase B always runs on 64 live lanes.
 // Phase B: float32 estimates of the r and mu bins, kept only when they lie
 // farther from every bin edge than their proven error (eps_r, eps_m, derived
-// in make_plan); every other pair is decided by the integer rule (int64
-// squared distance and edges, 128-bit mu cross-multiplication), which also
-// drops pairs that phase A's margin let through.  Bins go to a wave-private
-// uint32 LDS histogram flushed with uint64 global atomics when the wave
-// moves to another task.
+// in make_plan); every other pair goes to a second per-wave queue and is
+// decided by the integer rule (exact squared distances and edges, mu by
+// exact cross-multiplication), which also drops pairs that phase A's margin
+// let through.  Bins go to a uint32 LDS histogram shared by the block's
+// waves, flushed with uint64 global atomics when the block moves to another
+// task.
 #include <climits>
 #include <cstddef>
 #include <algorithm>

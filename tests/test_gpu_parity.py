@@ -356,6 +356,31 @@ def test_ragged_catalogues(torch, oracle_mod, lcmod):
             cells.close()
 
 
+def test_maximum_bins_bit_exact(torch, lcmod, oracle_mod):
+    """The largest histogram the library takes: 32 x 1024 = LC_MAX_BINS bins
+    (128 KB of LDS, room for one 4-wave block per CU), plane-parallel and
+    (r_p, pi), every task against the oracle; one bin more is refused."""
+    cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"], 2)
+    L = cats.wl.box_units
+    xyz = torch.from_numpy(cats.xyz).cuda()
+    tasks = [(0, 0), (0, 2), (1, 3), (2, 2)]
+    edges = list(range(0, 33 * 3 * mockgen.UNITS_PER_MPC, 3 * mockgen.UNITS_PER_MPC))
+    assert (len(edges) - 1) * 1024 == lcmod.LC_MAX_BINS
+    for los, pi_max, name in ((lcmod.LC_LOS_Z, 0, "z"), (lcmod.LC_LOS_RPPI, 40 * mockgen.UNITS_PER_MPC, "rppi")):
+        bn = lcmod.Binning(edges, 1024, True, L, los, pi_max)
+        cells = lcmod.lc_build_cells(xyz, cats.offsets, bn)
+        counts = torch.zeros((len(tasks), bn.n_r, 1024), dtype=torch.int64, device="cuda")
+        lcmod.lc_pair_count_batch(cells, tasks, bn, counts)
+        got = counts.cpu().numpy().view(np.uint64)
+        for t, (a, b) in enumerate(tasks):
+            ref = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), edges, 1024, L, name,
+                                         pi_max=pi_max)
+            assert np.array_equal(got[t], ref), (name, t)
+        cells.close()
+    with pytest.raises(lcmod.LcError):
+        lcmod.lc_build_cells(xyz, cats.offsets, lcmod.Binning(edges + [edges[-1] + 1], 1024, True, L))
+
+
 def test_out_of_box_coordinate_is_an_error(torch, lcmod):
     L = 1000
     xyz = torch.tensor([[1, 2, L], [3, 4, 5], [6, 7, 8]], dtype=torch.int32, device="cuda")
