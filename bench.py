@@ -36,13 +36,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def _code_only(src: str) -> str:
+    """C++ source with comments and blank space removed (string literals in
+    these files hold no comment markers)."""
+    import re
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def kernel_source_hash() -> str:
-    """sha256[:16] of the pair-count kernel's sources (paircount.hip, lc_internal.hpp)."""
+    """sha256[:16] of the pair-count kernel's code (paircount.hip and
+    lc_internal.hpp, comments and layout removed, so that only a change to
+    the code invalidates the measured traffic)."""
     import hashlib
     h = hashlib.sha256()
     for f in ("paircount.hip", "lc_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2205_11852_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2205_11852_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
