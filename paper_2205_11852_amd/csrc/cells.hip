@@ -341,8 +341,9 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     GridGeom g{};
     g.periodic = b->periodic;
     g.box = b->periodic ? b->box_units : 0;
-    unsigned* d_err = nullptr;
-    LC_TRY(dev_alloc((void**)&d_err, 64, s));
+    DevBuf<unsigned> errb;  // [0] error word, [8..13] bounding box
+    LC_TRY(errb.alloc(16, s));
+    unsigned* d_err = errb.get();
     k_zero_u32<<<1, 64, 0, s>>>(d_err, 16);
     if (b->periodic) {
         for (int a = 0; a < 3; a++) {
@@ -357,10 +358,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         unsigned h[16];
         LC_TRY_HIP(hipMemcpyAsync(h, d_err, sizeof h, hipMemcpyDeviceToHost, s));
         LC_TRY_HIP(hipStreamSynchronize(s));
-        if (h[0] & 1u) {
-            dev_free(d_err, s);
-            return fail(LC_ERR_RANGE, "a coordinate is outside |x| < 2^24");
-        }
+        if (h[0] & 1u) return fail(LC_ERR_RANGE, "a coordinate is outside |x| < 2^24");
         const int32_t* hb = (const int32_t*)(h + 8);
         for (int a = 0; a < 3; a++) {
             if (n_total == 0) {
@@ -420,7 +418,6 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         (void)hipGetLastError();
         free_cells_mem(cells);
         delete cells;
-        dev_free(d_err, s);
         return fail(LC_ERR_NOMEM, "mesh allocation (%zu + %zu bytes) failed", pts_bytes, cs_bytes);
     }
     cells->bytes = pts_bytes + cs_bytes;
@@ -445,7 +442,6 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         dev_free(d_gid, s);
         dev_free(d_cnt, s);
         dev_free(d_bsum, s);
-        dev_free(d_err, s);
         lc_free_cells(cells);
         return st;
     }
@@ -468,7 +464,6 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     dev_free(d_gid, s);
     dev_free(d_cnt, s);
     dev_free(d_bsum, s);
-    dev_free(d_err, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) {

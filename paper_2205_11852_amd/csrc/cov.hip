@@ -554,13 +554,15 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
         *mn = *mx = NAN;
         return LC_OK;
     }
-    double* W = nullptr;
-    double* aux = nullptr;
-    CheckFlags* fl = nullptr;
-    LC_TRY(dev_alloc((void**)&W, sizeof(double) * n * n, s));
+    DevBuf<double> Wb, auxb;
+    DevBuf<CheckFlags> flb;
+    LC_TRY(Wb.alloc(size_t(n * n), s));
     const int64_t naux = 6 * n + 16;
-    LC_TRY(dev_alloc((void**)&aux, sizeof(double) * naux, s));
-    LC_TRY(dev_alloc((void**)&fl, sizeof(CheckFlags) * 2, s));
+    LC_TRY(auxb.alloc(size_t(naux), s));
+    LC_TRY(flb.alloc(2, s));
+    double* W = Wb.get();
+    double* aux = auxb.get();
+    CheckFlags* fl = flb.get();
     k_zero_flags<<<1, 64, 0, s>>>(fl, 2);
     double* v = aux;
     double* pv = aux + n;
@@ -596,9 +598,6 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     double hr[3];
     LC_TRY_HIP(hipMemcpyAsync(hf, fl, sizeof hf, hipMemcpyDeviceToHost, s));
     LC_TRY_HIP(hipMemcpyAsync(hr, res, sizeof hr, hipMemcpyDeviceToHost, s));
-    dev_free(W, s);
-    dev_free(aux, s);
-    dev_free(fl, s);
     LC_TRY_HIP(hipStreamSynchronize(s));
     *chol_ok = (!hf[0].nan_seen && !hf[0].chol_fail) ? 1 : 0;
     *n_neg = int32_t(hr[2]);
@@ -624,17 +623,18 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
     const int64_t W3 = 3 * P;
     const double denom = double(N - 1);
     const int m_inf = std::isinf(M) ? 1 : 0;
-    double* mean = nullptr;
-    double* part = nullptr;
-    double* cov = nullptr;
-    double* Aw = A;
-    double* Bw = B;
-    LC_TRY(dev_alloc((void**)&mean, sizeof(double) * W3, s));
+    DevBuf<double> meanb, partb, covb, Ab, Bb;
+    LC_TRY(meanb.alloc(size_t(W3), s));
     const int64_t nchunk = (N + kMeanRows - 1) / kMeanRows;
-    LC_TRY(dev_alloc((void**)&part, sizeof(double) * W3 * nchunk, s));
-    LC_TRY(dev_alloc((void**)&cov, sizeof(double) * 3 * PP, s));
-    if (!Aw) LC_TRY(dev_alloc((void**)&Aw, sizeof(double) * PP, s));
-    if (!Bw) LC_TRY(dev_alloc((void**)&Bw, sizeof(double) * PP, s));
+    LC_TRY(partb.alloc(size_t(W3 * nchunk), s));
+    LC_TRY(covb.alloc(size_t(3 * PP), s));
+    if (!A) LC_TRY(Ab.alloc(size_t(PP), s));
+    if (!B) LC_TRY(Bb.alloc(size_t(PP), s));
+    double* mean = meanb.get();
+    double* part = partb.get();
+    double* cov = covb.get();
+    double* Aw = A ? A : Ab.get();
+    double* Bw = B ? B : Bb.get();
     {
         dim3 g(unsigned((W3 + 255) / 256), unsigned(nchunk));
         k_mean_partial<<<g, 256, 0, s>>>(xi, N, W3, part);
@@ -642,22 +642,20 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
     }
     const int64_t T64 = (P + 63) / 64;
     auto run_fp64 = [&](double* covbuf) -> lc_status {
-        double* dev = nullptr;
-        LC_TRY(dev_alloc((void**)&dev, sizeof(double) * 3 * N * P, s));
-        k_dev64<<<nblocks(3 * N * P, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, dev);
-        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 3), 256, 0, s>>>(dev, N, P, denom, covbuf);
-        dev_free(dev, s);
+        DevBuf<double> dev;
+        LC_TRY(dev.alloc(size_t(3 * N * P), s));
+        k_dev64<<<nblocks(3 * N * P, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, dev.get());
+        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 3), 256, 0, s>>>(dev.get(), N, P, denom, covbuf);
         return LC_OK;
     };
     auto run_fp32 = [&](double* covbuf) -> lc_status {
         const int64_t Npad = (N + kKT - 1) / kKT * kKT;
         const int64_t Ppad = (P + kMT - 1) / kMT * kMT;
-        float* dev = nullptr;
-        LC_TRY(dev_alloc((void**)&dev, sizeof(float) * 3 * Npad * Ppad, s));
-        k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, Npad, Ppad, dev);
+        DevBuf<float> dev;
+        LC_TRY(dev.alloc(size_t(3 * Npad * Ppad), s));
+        k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, Npad, Ppad, dev.get());
         const int64_t T = Ppad / kMT;
-        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev, Npad, Ppad, P, denom, covbuf);
-        dev_free(dev, s);
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev.get(), Npad, Ppad, P, denom, covbuf);
         return LC_OK;
     };
     if (precision == LC_FP64) {
@@ -668,23 +666,24 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
     k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, m_a, m_b, M, m_inf, Aw, Bw, C);
     double rel[3] = {-1.0, -1.0, -1.0};
     if (precision == LC_FP32_MFMA_CHECKED) {
-        double *A64 = nullptr, *B64 = nullptr, *C64 = nullptr, *fpart = nullptr;
-        LC_TRY(dev_alloc((void**)&A64, sizeof(double) * PP, s));
-        LC_TRY(dev_alloc((void**)&B64, sizeof(double) * PP, s));
-        LC_TRY(dev_alloc((void**)&C64, sizeof(double) * PP, s));
+        DevBuf<double> A64, B64, C64, fpart;
+        LC_TRY(A64.alloc(size_t(PP), s));
+        LC_TRY(B64.alloc(size_t(PP), s));
+        LC_TRY(C64.alloc(size_t(PP), s));
         const int nfb = 512;
-        LC_TRY(dev_alloc((void**)&fpart, sizeof(double) * 2 * nfb * 3, s));
+        LC_TRY(fpart.alloc(size_t(2 * nfb * 3), s));
         LC_TRY(run_fp64(cov));
-        k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, m_a, m_b, M, m_inf, A64, B64, C64);
-        k_frob<<<nfb, 256, 0, s>>>(C, C64, PP, fpart);
-        k_frob<<<nfb, 256, 0, s>>>(Aw, A64, PP, fpart + 2 * nfb);
-        k_frob<<<nfb, 256, 0, s>>>(Bw, B64, PP, fpart + 4 * nfb);
+        k_combine<<<nblocks(PP, 256, 65536), 256, 0, s>>>(cov, PP, m_a, m_b, M, m_inf, A64.get(), B64.get(),
+                                                          C64.get());
+        k_frob<<<nfb, 256, 0, s>>>(C, C64.get(), PP, fpart.get());
+        k_frob<<<nfb, 256, 0, s>>>(Aw, A64.get(), PP, fpart.get() + 2 * nfb);
+        k_frob<<<nfb, 256, 0, s>>>(Bw, B64.get(), PP, fpart.get() + 4 * nfb);
         std::vector<double> h(2 * nfb * 3);
-        LC_TRY_HIP(hipMemcpyAsync(h.data(), fpart, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        dev_free(A64, s);
-        dev_free(B64, s);
-        dev_free(C64, s);
-        dev_free(fpart, s);
+        LC_TRY_HIP(hipMemcpyAsync(h.data(), fpart.get(), sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+        A64.reset();
+        B64.reset();
+        C64.reset();
+        fpart.reset();
         LC_TRY_HIP(hipStreamSynchronize(s));
         for (int q = 0; q < 3; q++) {
             double num = 0, den = 0;
@@ -697,9 +696,9 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(LC_ERR_HIP, "covariance launch failed: %s", hipGetErrorString(e));
-    dev_free(mean, s);
-    dev_free(part, s);
-    dev_free(cov, s);
+    meanb.reset();
+    partb.reset();
+    covb.reset();
     if (rep) {
         rep->rel_frob_vs_fp64[0] = rel[0];
         rep->rel_frob_vs_fp64[1] = rel[1];
@@ -709,8 +708,6 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
         LC_TRY(check_block(C, P, split, P - split, s, &rep->chol_ok[1], &rep->n_neg_eig[1], &rep->min_eig[1],
                            &rep->max_eig[1]));
     }
-    if (!A) dev_free(Aw, s);
-    if (!B) dev_free(Bw, s);
     return LC_OK;
 }
 
@@ -760,36 +757,33 @@ extern "C" lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32
     hipStream_t s = (hipStream_t)stream;
     const int64_t N = n_mock, PL = P;
     const double denom = double(N - 1);
-    double* mean = nullptr;
-    double* part = nullptr;
-    LC_TRY(dev_alloc((void**)&mean, sizeof(double) * PL, s));
+    DevBuf<double> meanb, partb;
+    LC_TRY(meanb.alloc(size_t(PL), s));
     const int64_t nchunk = (N + kMeanRows - 1) / kMeanRows;
-    LC_TRY(dev_alloc((void**)&part, sizeof(double) * PL * nchunk, s));
+    LC_TRY(partb.alloc(size_t(PL * nchunk), s));
+    double* mean = meanb.get();
+    double* part = partb.get();
     {
         dim3 g(unsigned((PL + 255) / 256), unsigned(nchunk));
         k_mean_partial<<<g, 256, 0, s>>>(x, N, PL, part);
         k_mean_final<<<unsigned((PL + 255) / 256), 256, 0, s>>>(part, nchunk, PL, N, mean);
     }
     if (precision == LC_FP64) {
-        double* dev = nullptr;
-        LC_TRY(dev_alloc((void**)&dev, sizeof(double) * N * PL, s));
-        k_dev64<<<nblocks(N * PL, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, dev);
+        DevBuf<double> dev;
+        LC_TRY(dev.alloc(size_t(N * PL), s));
+        k_dev64<<<nblocks(N * PL, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, dev.get());
         const int64_t T64 = (PL + 63) / 64;
-        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 1), 256, 0, s>>>(dev, N, PL, denom, C);
-        dev_free(dev, s);
+        k_syrk64<<<dim3(unsigned(T64 * (T64 + 1) / 2), 1), 256, 0, s>>>(dev.get(), N, PL, denom, C);
     } else {
         const int64_t Npad = (N + kKT - 1) / kKT * kKT;
         const int64_t Ppad = (PL + kMT - 1) / kMT * kMT;
-        float* dev = nullptr;
-        LC_TRY(dev_alloc((void**)&dev, sizeof(float) * Npad * Ppad, s));
-        k_dev32<<<nblocks(Npad * Ppad, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, Npad, Ppad, dev);
+        DevBuf<float> dev;
+        LC_TRY(dev.alloc(size_t(Npad * Ppad), s));
+        k_dev32<<<nblocks(Npad * Ppad, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, Npad, Ppad, dev.get());
         const int64_t T = Ppad / kMT;
-        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 1), 256, 0, s>>>(dev, Npad, Ppad, PL, denom, C);
-        dev_free(dev, s);
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 1), 256, 0, s>>>(dev.get(), Npad, Ppad, PL, denom, C);
     }
     hipError_t e = hipGetLastError();
-    dev_free(mean, s);
-    dev_free(part, s);
     if (e != hipSuccess) return fail(LC_ERR_HIP, "covariance launch failed: %s", hipGetErrorString(e));
     return LC_OK;
 }

@@ -72,21 +72,18 @@ extern "C" lc_status lc_covcov(const double* A, const double* B, int32_t P, int3
     (void)ctx;
     hipStream_t s = (hipStream_t)stream;
     const int nblk = 512;
-    double* part = nullptr;
-    LC_TRY(dev_alloc((void**)&part, sizeof(double) * 2 * nblk, s));
+    DevBuf<double> partb;
+    LC_TRY(partb.alloc(size_t(2 * nblk), s));
+    double* part = partb.get();
     const double inv_m = std::isinf(M) ? 0.0 : 1.0 / M;
     const double f = 1.0 / (2.0 * m_a) - inv_m;
     const double inv_n1 = n_mock >= 2 ? 1.0 / double(n_mock - 1) : 0.0;
     k_covcov<<<nblk, 256, 0, s>>>(A, B, Cref, P, 1.0 / (2.0 * m_a), inv_m, f * f, inv_n1, sd_lc, sd_smp, part);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        dev_free(part, s);
-        return fail(LC_ERR_HIP, "covcov launch failed: %s", hipGetErrorString(e));
-    }
+    if (e != hipSuccess) return fail(LC_ERR_HIP, "covcov launch failed: %s", hipGetErrorString(e));
     if (rep) {
         std::vector<double> h(2 * nblk);
         LC_TRY_HIP(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
-        dev_free(part, s);
         LC_TRY_HIP(hipStreamSynchronize(s));
         double lc_sum = 0.0, smp_sum = 0.0;
         for (int b = 0; b < nblk; b++) {
@@ -101,8 +98,6 @@ extern "C" lc_status lc_covcov(const double* A, const double* B, int32_t P, int3
         rep->ifom_lc = rep->cost_lc * rep->chi2_2_lc;
         rep->ifom_smp = rep->cost_smp * rep->chi2_2_smp;
         rep->gain = rep->ifom_smp / rep->ifom_lc;
-    } else {
-        dev_free(part, s);
     }
     return LC_OK;
 }

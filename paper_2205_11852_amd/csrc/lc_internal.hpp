@@ -74,6 +74,32 @@ class Stager {
 lc_status dev_alloc(void** p, size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
 
+// A stream-ordered device buffer that is freed on its stream when it goes
+// out of scope (or at reset()), so every early return releases what was
+// allocated before it.
+template <typename T>
+class DevBuf {
+  public:
+    DevBuf() = default;
+    ~DevBuf() { reset(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    lc_status alloc(size_t n, hipStream_t s) {
+        reset();
+        s_ = s;
+        return dev_alloc(reinterpret_cast<void**>(&p_), sizeof(T) * n, s);
+    }
+    void reset() {
+        dev_free(p_, s_);
+        p_ = nullptr;
+    }
+    T* get() const { return p_; }
+
+  private:
+    T* p_ = nullptr;
+    hipStream_t s_ = nullptr;
+};
+
 // ---------------------------------------------------------------------------
 // geometry shared by the mesh and the pair kernels
 // ---------------------------------------------------------------------------
