@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--tune-sample", type=int, default=64, help="tasks timed by the autotuner")
     ap.add_argument("--slab-mocks", type=int, default=100,
                     help="mocks of the paper-shaped slab workload timed after the main line (0: skip)")
+    ap.add_argument("--slab-only", action="store_true",
+                    help="time only the paper-shaped slab workload and print its JSON object (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this path has no multi-GPU mode "
@@ -191,6 +193,10 @@ def main():
     import mockgen
     from paper_2205_11852_amd import lc
     from paper_2205_11852_amd.pipeline import Pipeline
+
+    if args.slab_only:
+        print(json.dumps(paper_slab(args, torch, lc, torch.cuda.current_stream())))
+        return
 
     wl = mockgen.WORKLOADS[args.config]
     n_mock = args.mocks or wl.n_mock
