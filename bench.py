@@ -162,6 +162,62 @@ def paper_slab(args, torch, lc, stream) -> dict:
                     "chi^2_2 normalised by C = A + B/M" % wl.n_mock}
 
 
+def covariance_precision(args, torch, lc) -> dict:
+    """The covariance-precision workload (c5: 5000 mocks of 5e4 points, the
+    40 x 50 (r, mu) vector plus multipoles, P = 2120): counts and data vectors
+    on the GPU, then the covariance with float32-MFMA products against the
+    float64 path on the same vectors: relative Frobenius error of C^LC, A and
+    B, and the error of the extreme eigenvalues of each block of C^LC."""
+    import dataclasses
+
+    import mockgen
+    from paper_2205_11852_amd.pipeline import Pipeline
+
+    wl = dataclasses.replace(mockgen.WORKLOADS["c5"], n_mock=args.c5_mocks)
+    t0 = time.perf_counter()
+    cats = mockgen.make_catalogues(wl)
+    log("[c5] generated %d mocks, %d points in %.1f s" % (wl.n_mock, cats.xyz.shape[1], time.perf_counter() - t0))
+    pl = Pipeline(cats)
+    stream = torch.cuda.current_stream()
+    pl.build_cells()
+    pl.count()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pl.count()
+    e1.record(stream)
+    pl.xi_multipoles()
+    torch.cuda.synchronize()
+    count_ms = e0.elapsed_time(e1)
+    t = {}
+    reps = {}
+    for name, prec, checked in (("fp32_mfma", lc.LC_FP32_MFMA, lc.LC_FP32_MFMA_CHECKED),
+                                ("fp64", lc.LC_FP64, lc.LC_FP64)):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        pl.covariance(prec, report=False)
+        b.record(stream)
+        torch.cuda.synchronize()
+        t[name] = a.elapsed_time(b)
+        # the report: the check of C^LC, and for float32 its float64 twin's errors
+        reps[name] = pl.covariance(checked, report=True)
+    r32, r64 = reps["fp32_mfma"], reps["fp64"]
+    eig = []
+    for blk in range(2):
+        scale = max(abs(r64["min_eig"][blk]), abs(r64["max_eig"][blk]))
+        eig.append(max(abs(r32["min_eig"][blk] - r64["min_eig"][blk]),
+                       abs(r32["max_eig"][blk] - r64["max_eig"][blk])) / scale)
+    return {"workload": "c5: %d mocks x Poisson(%g), %g Mpc/h periodic box, %d x %d randoms, %d x %d bins, P = %d"
+                        % (wl.n_mock, wl.n_mean, wl.box_mpc, wl.n_subsets, wl.subset_size, wl.n_r, wl.n_mu,
+                           pl.binning.P),
+            "pair_count_ms": count_ms, "mocks_per_hour_pair_count": wl.n_mock * 3600.0 / (count_ms / 1e3),
+            "covariance_ms": t, "rel_frob_fp32_vs_fp64": {"C": r32["rel_frob_vs_fp64"][0],
+                                                          "A": r32["rel_frob_vs_fp64"][1],
+                                                          "B": r32["rel_frob_vs_fp64"][2]},
+            "max_eig_error_rel": {"xi_block": eig[0], "multipole_block": eig[1]},
+            "report_fp32": r32, "report_fp64": r64}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -179,6 +235,8 @@ def main():
     ap.add_argument("--tune-sample", type=int, default=64, help="tasks timed by the autotuner")
     ap.add_argument("--slab-mocks", type=int, default=100,
                     help="mocks of the paper-shaped slab workload timed after the main line (0: skip)")
+    ap.add_argument("--c5-mocks", type=int, default=5000,
+                    help="mocks of the covariance-precision workload (c5) reported after the main line (0: skip)")
     ap.add_argument("--slab-only", action="store_true",
                     help="time only the paper-shaped slab workload and print its JSON object (for profiling)")
     args = ap.parse_args()
@@ -352,6 +410,10 @@ def main():
                                "lc_pair_count_s_per_mock": lc_mock, "ratio": direct / lc_mock,
                                "pair_ratio_model": model,
                                "note": "RR of the shared sub-catalogues amortised over all mocks in both"}
+
+    if args.c5_mocks > 1:
+        log("[bench] covariance precision (c5)")
+        out["covariance_precision_c5"] = covariance_precision(args, torch, lc)
 
     if args.slab_mocks > 0:
         log("[bench] paper-shaped slab workload")
