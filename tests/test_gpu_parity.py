@@ -651,3 +651,69 @@ def test_general_vectors_and_strided_split(c1, torch, lcmod, oracle_mod):
             scale = (np.abs(x2)[:, None, :] * np.abs(W)[None, :, :]).sum(axis=2).T.ravel()
             fin = np.isfinite(V[nb:])
             assert np.all(np.abs(g[m, e, nb:] - V[nb:])[fin] <= 1e-12 * scale[fin] + 1e-300)
+
+
+def _random_config(r):
+    """One random but valid binning, geometry, mesh and launch shape."""
+    periodic = bool(r.integers(0, 2))
+    los = ["z", "mid", "rppi"][int(r.integers(0, 3))]
+    if los == "mid":
+        periodic = False
+    L = int(r.integers(20000, 200000)) * 2 if periodic else 0
+    span = L if periodic else int(r.integers(20000, 400000))
+    lo = 0 if periodic else int(r.integers(-(1 << 22), 1 << 22))
+    reach = (L // 2 - 1) if periodic else span
+    n_r = int(r.integers(1, 25))
+    rmax = int(r.integers(max(n_r + 2, span // 40), max(n_r + 3, min(reach, span // 3))))
+    if r.random() < 0.5:
+        e0 = int(r.integers(0, rmax // 4 + 1)) if r.random() < 0.5 else 0
+        de = max(1, (rmax - e0) // n_r)
+        edges = [e0 + k * de for k in range(n_r + 1)]
+    else:
+        edges = sorted(set(int(v) for v in r.integers(0, rmax, size=n_r + 1)))
+        if len(edges) < 2:
+            edges = [0, rmax]
+    n_mu = int(r.integers(1, 60))
+    pi_max = int(r.integers(1, max(2, min(reach, span // 3)))) if los == "rppi" else 0
+    cell = int(r.integers(0, 2)) * int(r.integers(max(1, edges[-1] // 4), max(2, edges[-1] + 1)))
+    sub = [0, 1, 2, 4][int(r.integers(0, 4))]
+    tune = dict(chunk=4 * int(r.integers(1, 17 if los == "mid" else 65)),
+                waves_per_block=[0, 1, 2, 4, 8, 16][int(r.integers(0, 6))],
+                cells_per_item=int(r.integers(0, 5)))
+    return dict(periodic=periodic, los=los, L=L, lo=lo, span=span, edges=edges, n_mu=n_mu, pi_max=pi_max,
+                cell=cell, sub=sub, tune=tune)
+
+
+@pytest.mark.parametrize("seed", range(60))
+def test_random_configurations_bit_exact(torch, lcmod, oracle_mod, seed):
+    """Seeded random binnings (uniform or not, e_0 >= 0, 1-59 mu bins),
+    geometries (periodic boxes, open regions anywhere in |x| < 2^24),
+    lines of sight (z, midpoint, (r_p, pi)), meshes and launch shapes, on
+    clustered and uniform catalogues: every task bit-exact."""
+    r = np.random.default_rng(1000 + seed)
+    cfg = _random_config(r)
+    _say("[random]", seed, {k: v for k, v in cfg.items() if k != "edges"}, "n_r", len(cfg["edges"]) - 1)
+    cats = []
+    for c in range(3):
+        n = int(r.integers(0, 900)) if c else int(r.integers(200, 1500))
+        if r.random() < 0.5:   # clustered around a few centres
+            centres = r.integers(0, cfg["span"], size=(3, 6))
+            pts = centres[:, r.integers(0, 6, size=n)] + r.normal(0, cfg["span"] / 30, size=(3, n)).astype(np.int64)
+            pts = np.clip(pts, 0, cfg["span"] - 1)
+        else:
+            pts = r.integers(0, cfg["span"], size=(3, n))
+        cats.append((pts + cfg["lo"]).astype(np.int32) if not cfg["periodic"] else (pts % cfg["L"]).astype(np.int32))
+    off = np.cumsum([0] + [c.shape[1] for c in cats])
+    xyz = torch.from_numpy(np.ascontiguousarray(np.concatenate(cats, axis=1))).cuda()
+    los = {"z": lcmod.LC_LOS_Z, "mid": lcmod.LC_LOS_MID, "rppi": lcmod.LC_LOS_RPPI}[cfg["los"]]
+    bn = lcmod.Binning(cfg["edges"], cfg["n_mu"], cfg["periodic"], cfg["L"], los, cfg["pi_max"])
+    cells = lcmod.lc_build_cells(xyz, off, bn, cfg["cell"], cfg["sub"])
+    tasks = [(a, b) for a in range(3) for b in range(3)]
+    counts = torch.zeros((len(tasks), bn.n_r, bn.n_mu), dtype=torch.int64, device="cuda")
+    lcmod.lc_pair_count_batch(cells, tasks, bn, counts, lcmod.LC_PERSISTENT, cfg["tune"])
+    got = counts.cpu().numpy().view(np.uint64)
+    for t, (a, b) in enumerate(tasks):
+        ref = oracle_mod.count_pairs(cats[a], None if a == b else cats[b], cfg["edges"], cfg["n_mu"], cfg["L"],
+                                     cfg["los"], pi_max=cfg["pi_max"])
+        assert np.array_equal(got[t], ref), (seed, t)
+    cells.close()
