@@ -30,6 +30,8 @@ PEAK_OPS = 256 * 64 * 2.4e9
 # distance and range test (~14 ops), exact r and mu bin (~20 ops), one
 # histogram increment.
 OPS_PER_BINNED_PAIR = 35
+# Pair tests the CPU baseline runs at most (about 10-30 s on 8-16 host cores).
+CPU_SAMPLE_TESTS = 3.0e10
 
 
 def log(*a):
@@ -74,6 +76,24 @@ def measured_traffic(config: str, n_mock: int, wl_mocks: int):
     if kv.get("kernel_source") != kernel_source_hash() or "traffic_bytes_per_launch" not in kv:
         return None
     return int(kv["traffic_bytes_per_launch"])
+
+
+def workload_text(wl, n_mock: int) -> str:
+    """What a workload is, with its sizes."""
+    if wl.geometry == "periodic":
+        where = "%g Mpc/h periodic box" % wl.box_mpc
+    elif wl.geometry == "wedge":
+        where = "open 60x60 deg wedge, comoving distance 1200-2400 Mpc/h, n(chi) falling 3x"
+    else:
+        where = "open 1500x1500x300 Mpc/h slab"
+    if wl.per_mock_randoms:
+        rnd = "two random sub-catalogues of each mock's size"
+    else:
+        rnd = "shared pool of %d x %d randoms" % (wl.n_subsets, wl.subset_size)
+    los = {"z": "z line of sight", "mid": "midpoint line of sight",
+           "rppi": "(r_p, pi) along z"}[wl.los]
+    return ("%s: %d mocks x Poisson(%g) clustered galaxies, %s, %s, %d r-bins to %g Mpc/h x %d mu-bins, %s"
+            % (wl.name, n_mock, wl.n_mean, where, rnd, wl.n_r, wl.r_max_mpc, wl.n_mu, los))
 
 
 def paper_slab(args, torch, lc, stream) -> dict:
@@ -260,7 +280,7 @@ def main():
     n_mock = args.mocks or wl.n_mock
     t0 = time.perf_counter()
     log("[bench] generating %s with %d mocks" % (wl.name, n_mock))
-    cats = mockgen.make_catalogues(wl, n_mock)
+    cats = mockgen.make_catalogues(wl, n_mock, progress=log)
     log("[bench] generated %d points in %.1f s" % (cats.xyz.shape[1], time.perf_counter() - t0))
     pl = Pipeline(cats)
     cell_units = int(args.cell_mpc * mockgen.UNITS_PER_MPC)
@@ -319,10 +339,7 @@ def main():
         "vs_baseline": None,
         "dtype": "int64/f64 (pair counts exact; covariance f32-MFMA products, f64 combination)",
         "data": "synthetic (seeded Neyman-Scott mocks and uniform randoms)",
-        "config": {"workload": "%s: %d mocks x Poisson(%g) clustered galaxies, %g Mpc/h periodic box, "
-                               "%d x %d randoms, %d r-bins to %g Mpc/h x %d mu-bins, %s line of sight"
-                               % (wl.name, n_mock, wl.n_mean, wl.box_mpc, wl.n_subsets, wl.subset_size,
-                                  wl.n_r, wl.r_max_mpc, wl.n_mu, wl.los),
+        "config": {"workload": workload_text(wl, n_mock),
                    "n_tasks": int(len(pl.tasks)), "cells": pl.cells.info()["grid"],
                    "sub_cells": pl.cells.info()["sub"], "autotuned": tuned},
         "pair_tests_per_s": cand / kern_s,
@@ -425,22 +442,37 @@ def main():
         log("[bench] cpu baseline (oracle) on mock 0")
         e = pl.est[0]
         D, R1, R2 = pl.tasks[e[0]][0], pl.tasks[e[1]][1], pl.tasks[e[2]][1]
-        t0 = time.perf_counter()
-        for a, b in ((D, None), (D, R1), (D, R2)):
-            oracle.count_pairs(cats.cat(a), None if b is None else cats.cat(b), wl.r_edges_units, wl.n_mu,
-                               wl.box_units, wl.los)
-        t_cpu = time.perf_counter() - t0
         n_d = int(pl.sizes[D])
-        tests = n_d * (n_d - 1) / 2 + n_d * (pl.sizes[R1] + pl.sizes[R2])
-        # a shared random sub-catalogue's RR is counted once for the whole batch
-        rr_share = len(set(pl.est[:, 3:].ravel().tolist())) / n_mock
-        t_mock = t_cpu * (1.0 + rr_share * (wl.subset_size ** 2 / 2) / tests)
+        full = n_d * (n_d - 1) / 2 + n_d * float(pl.sizes[R1] + pl.sizes[R2])
+        # RR per mock: a shared sub-catalogue's RR is counted once for the
+        # whole batch, per-mock sub-catalogues once per mock
+        rr_tests = sum(float(pl.sizes[pl.tasks[t][0]]) * (pl.sizes[pl.tasks[t][0]] - 1) / 2
+                       for t in set(pl.est[:, 3:].ravel().tolist())) / n_mock
+        t0 = time.perf_counter()
+        if full <= CPU_SAMPLE_TESTS:
+            for a, b in ((D, None), (D, R1), (D, R2)):
+                oracle.count_pairs(cats.cat(a), None if b is None else cats.cat(b), wl.r_edges_units, wl.n_mu,
+                                   wl.box_units, wl.los)
+            tests = full
+            what = "brute-force DD, DR1, DR2 of mock 0"
+        else:
+            # a bounded sample: the first n_s points of mock 0 against all of
+            # mock 0, R1 and R2 (every test costs the same in the oracle)
+            n_s = max(1, int(CPU_SAMPLE_TESTS / (n_d + float(pl.sizes[R1] + pl.sizes[R2]))))
+            head = cats.cat(D)[:, :n_s]
+            for b in (D, R1, R2):
+                oracle.count_pairs(head, cats.cat(b), wl.r_edges_units, wl.n_mu, wl.box_units, wl.los)
+            tests = n_s * (n_d + float(pl.sizes[R1] + pl.sizes[R2]))
+            what = ("brute-force cross counts of %d points of mock 0 against mock 0, R1 and R2, "
+                    "scaled to the %.2e tests of its DD, DR1, DR2" % (n_s, full))
+        t_cpu = time.perf_counter() - t0
+        rate = tests / t_cpu
+        t_mock = (full + rr_tests) / rate
         out["cpu_baseline"] = {"value": 3600.0 / t_mock, "unit": "mocks/hour",
                                "cores": oracle.threads_used(), "kind": "oracle",
-                               "sample": "brute-force DD, DR1, DR2 of mock 0 (%.2e pair tests, %.1f s) plus "
-                                         "its share of the shared RR counts; LS/covariance excluded"
-                                         % (tests, t_cpu),
-                               "pair_tests_per_s": tests / t_cpu}
+                               "sample": "%s (%.2e pair tests, %.1f s) plus its share of the RR counts; "
+                                         "LS/covariance excluded" % (what, tests, t_cpu),
+                               "pair_tests_per_s": rate}
     print(json.dumps(out))
 
 

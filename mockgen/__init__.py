@@ -19,7 +19,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import List, Optional, Tuple
+from typing import Callable, List, Optional, Tuple
 
 import numpy as np
 
@@ -285,15 +285,21 @@ def subset_pair(wl: Workload, m: int) -> Tuple[int, int]:
     return (2 * m) % k, (2 * m + 1) % k
 
 
-def make_catalogues(wl: Workload, n_mock: Optional[int] = None) -> Catalogues:
+def make_catalogues(wl: Workload, n_mock: Optional[int] = None,
+                    progress: Optional[Callable[[str], None]] = None) -> Catalogues:
     """Draw every catalogue of a workload.
 
     Layout: mocks 0..n_mock-1, then the random sub-catalogues.  With a shared
     pool only the sub-catalogues some mock uses are drawn (pool index k is
     seeded by k, so a subset of mocks sees the same randoms as the full run).
+    progress: called with a short message every 50 mocks (long workloads).
     """
     n_mock = wl.n_mock if n_mock is None else int(n_mock)
-    cats = [mock_catalogue(wl, m) for m in range(n_mock)]
+    cats = []
+    for m in range(n_mock):
+        cats.append(mock_catalogue(wl, m))
+        if progress is not None and (m + 1) % 50 == 0:
+            progress("%s: %d of %d mocks drawn" % (wl.name, m + 1, n_mock))
     randoms = np.zeros((n_mock, 2), dtype=np.int64)
     if wl.per_mock_randoms:
         for m in range(n_mock):

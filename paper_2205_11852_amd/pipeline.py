@@ -115,7 +115,10 @@ def block_rebin_map(n_blocks: int, n: int, w: int) -> Tuple[np.ndarray, np.ndarr
 class Pipeline:
     """Device-resident catalogues of one workload and the calls of the path."""
 
-    def __init__(self, cats, device: str = "cuda", M: float = 50.0, m_a: int = 1):
+    def __init__(self, cats, device: str = "cuda", M: float = 50.0, m_a: int = 1,
+                 extra_tasks: Optional[Sequence[Tuple[int, int]]] = None):
+        """extra_tasks: further (cat_a, cat_b) pairs counted in the same
+        launches after the estimator's tasks (ids from len(plan) on)."""
         import torch
         self.torch = torch
         self.cats = cats
@@ -123,6 +126,9 @@ class Pipeline:
         self.device = device
         self.binning = lc.Binning.from_workload(self.wl)
         self.tasks, self.est = plan_tasks(cats.n_mock, cats.randoms)
+        if extra_tasks is not None and len(extra_tasks):
+            ex = np.asarray(extra_tasks, dtype=np.int32).reshape(-1, 2)
+            self.tasks = np.concatenate([self.tasks, ex], axis=0)
         self.sizes = cats.sizes()
         self.offsets = cats.offsets
         self.M = float(M)
