@@ -110,7 +110,10 @@ typedef struct {
  *   out          receives the mesh; free with lc_free_cells.
  * Synchronises `stream` (once for a periodic box, twice for open geometry:
  * the bounding box, then the device range-check word).  A point outside the
- * geometry returns LC_ERR_RANGE and no mesh.
+ * geometry returns LC_ERR_RANGE and no mesh.  With LC_LOS_MID the mesh also
+ * keeps the points' absolute coordinates (twice the point memory) and every
+ * catalogue must hold fewer than 2^28 points (else LC_ERR_OVERFLOW); pair
+ * counting with LC_LOS_MID needs such a mesh.
  */
 lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
                          int32_t n_cat, const lc_binning* b, const lc_mesh_opts* opts,
@@ -152,7 +155,7 @@ typedef struct {
                                  single task's few items finish sooner with more waves each) */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
     int32_t chunk;            /* i points tested together against each gathered j set:
-                                 a multiple of 4 in [4, 256] ([4, 64] for LC_LOS_MID);
+                                 a multiple of 4 in [4, 256];
                                  default the maximum */
 } lc_tuning;
 

@@ -114,7 +114,6 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
     for (int32_t i = 0; i < ns; i++) sample.push_back(tasks[int64_t(i) * n_tasks / ns]);
 
     const int64_t rmax = mesh_reach(b);
-    const bool mid = b->los == LC_LOS_MID;
     const int nbins = b->n_r * b->n_mu;
     uint64_t* counts = nullptr;
     LC_TRY(dev_alloc((void**)&counts, size_t(ns) * nbins * sizeof(uint64_t), s));
@@ -159,7 +158,7 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
     constexpr double kGain = 0.02;
     // stage 1: mesh (cell side x sub-cell split) at the default launch shape;
     // the first width is the default one and sub = 2 the default split
-    const int chunk0 = mid ? 64 : 256;
+    const int chunk0 = 256;
     lc_mesh_opts best_mesh{};
     for (size_t iw = 0; iw < widths.size() && st == LC_OK; iw++) {
         for (int sub : {2, 1, 4}) {
@@ -188,7 +187,7 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
         lc_cells* c = nullptr;
         st = lc_build_cells(xyz, n_total, cat_offsets, n_cat, b, &best_mesh, s, &c);
         if (st == LC_OK) {
-            const std::vector<int> chunks = mid ? std::vector<int>{32, 64} : std::vector<int>{64, 128, 256};
+            const std::vector<int> chunks = {64, 128, 256};
             for (int ch : chunks) {
                 if (ch == chunk0) continue;
                 lc_tuning tn{};

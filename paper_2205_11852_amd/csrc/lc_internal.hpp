@@ -14,6 +14,11 @@
 
 namespace lc {
 
+// Midpoint line of sight: points per catalogue stay below 2^28, so that a
+// pair's i index within its catalogue (kept in a 32-bit queue slot) times
+// 12 bytes is a 32-bit offset into the catalogue's absolute coordinates.
+constexpr int64_t kMidMaxCatalogue = int64_t(1) << 28;
+
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
@@ -138,6 +143,9 @@ struct lc_cells {
     int32_t los = 0;
     int64_t r_max = 0;              // largest r edge the mesh was built for
     float* pts = nullptr;           // sorted points, float32 (x, y, z) relative to their cell origin
+    // midpoint meshes only: the same points' absolute coordinates (float32,
+    // exact below 2^24), read when a pair's line of sight is binned
+    float* apts = nullptr;
     // starts of the sub-cells, [n_cat][ncell][nsub] + 1 (global point index);
     // coarse cell c of catalogue k spans [cs[(k ncell + c) nsub], cs[(k ncell + c + 1) nsub])
     int64_t* cs = nullptr;

@@ -220,7 +220,9 @@ struct WaveState {
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
-    int* itab;            // midpoint: absolute coordinates of the chunk's i points (block)
+    const float* ai;      // midpoint: absolute coordinates of the task's i catalogue (wave-uniform)
+    uint32_t ai_last;     // midpoint: that catalogue's size - 1 (clamp of queued i indices)
+    int64_t a0;           // midpoint: global index of the catalogue's first point
     float4* xa;           // this wave's queue of pairs for the integer rule, entries [0, xn)
     uint32_t xn;          // wave-uniform
     uint32_t qtail;       // wave-uniform
@@ -247,8 +249,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // fail the test, so every value stays finite.  (A bound below 0 sends every
 // pair to the integer rule.)
 template <int LOS, bool UNIFORM, bool HAS_E0>
-__device__ __forceinline__ uint32_t bin_fast(const float4 e, const int* __restrict__ itab, const PcParams& p,
-                                             float& fm, float& fr) {
+__device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
+                                             const PcParams& p, float& fm, float& fr) {
     // Each estimate is shifted down by its margin eps inside the FMA that
     // forms it, x' = x - eps.  Then fract(x') < 1 - 2 eps (one compare)
     // holds only when x lies in (floor(x') + eps', floor(x') + 1 - eps') with
@@ -268,18 +270,21 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const int* __restri
         rs = __builtin_amdgcn_rsqf(d2f);
         u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
-        // l = x_i + x_j = 2 x_i + s, all integers: p = s.l and q = l.l are
-        // exact in float64 (< 2^53).  The i index is clamped so that a lane
-        // past the drained entries (masked by the caller) reads inside the table.
-        const int il = min(max(__float_as_int(e.w), 0), 63);
-        const double lx = 2.0 * double(itab[3 * il]) + double(e.x);
-        const double ly = 2.0 * double(itab[3 * il + 1]) + double(e.y);
-        const double lz = 2.0 * double(itab[3 * il + 2]) + double(e.z);
-        const double P = fma(double(e.x), lx, fma(double(e.y), ly, double(e.z) * lz));
-        const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
+        // l = x_i + x_j = 2 x_i + s from the i point's absolute coordinates;
+        // e.w holds its index within the task's i catalogue, clamped so that
+        // a lane past the drained entries (masked by the caller) reads inside
+        // the catalogue.  l, p = s.l and q = l.l in float32, within the error
+        // bound that make_plan's mu margin covers.
+        const uint32_t il = min(uint32_t(__float_as_int(e.w)), ai_last);
+        const float* xi = ai + il * 3u;
+        const float lx = fmaf(2.0f, xi[0], e.x);
+        const float ly = fmaf(2.0f, xi[1], e.y);
+        const float lz = fmaf(2.0f, xi[2], e.z);
+        const float P = fmaf(e.x, lx, fmaf(e.y, ly, e.z * lz));
+        const float Q = fmaf(lx, lx, fmaf(ly, ly, lz * lz));
         d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
         rs = __builtin_amdgcn_rsqf(d2f);
-        u = fmaf(fabsf(float(P)) * rs * __builtin_amdgcn_rsqf(fmaxf(float(Q), 1.0f)), p.nmuf, -p.mu_shift);
+        u = fmaf(fabsf(P) * rs * __builtin_amdgcn_rsqf(fmaxf(Q, 1.0f)), p.nmuf, -p.mu_shift);
     }
     // |mu| n_mu <= n_mu exactly; an estimate within eps_m of n_mu (mu near 1)
     // fails the test, so m < n_mu whenever the pair is kept
@@ -301,7 +306,7 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const int* __restri
 // Histogram slot of one queued pair by the integer rule (discard slot when it
 // lies outside [e_0, e_n)); the float64 estimates only seed the searches.
 template <int LOS, bool UNIFORM>
-__device__ __forceinline__ int exact_entry(const float4 e, const int* __restrict__ itab,
+__device__ __forceinline__ int exact_entry(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
                                            const ExactTab* __restrict__ xt) {
     const double x = e.x, y = e.y, z = e.z;
     const double d2 = fma(x, x, fma(y, y, z * z));
@@ -316,10 +321,12 @@ __device__ __forceinline__ int exact_entry(const float4 e, const int* __restrict
         const int m_est = d2 > 0.0 ? int(fabs(z) / r * double(xt->n_mu)) : 0;
         return exact_bin_z<UNIFORM>(x, y, z, k_est, m_est, xt);
     }
-    const int il = __float_as_int(e.w);
-    const double lx = 2.0 * double(itab[3 * il]) + x;
-    const double ly = 2.0 * double(itab[3 * il + 1]) + y;
-    const double lz = 2.0 * double(itab[3 * il + 2]) + z;
+    // exact: absolute coordinates and separations are integers, l below 2^26
+    const uint32_t il = min(uint32_t(__float_as_int(e.w)), ai_last);
+    const float* xi = ai + il * 3u;
+    const double lx = 2.0 * double(xi[0]) + x;
+    const double ly = 2.0 * double(xi[1]) + y;
+    const double lz = 2.0 * double(xi[2]) + z;
     const double P = fma(x, lx, fma(y, ly, z * lz));
     const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
     const int m_est = (d2 > 0.0 && Q > 0.0) ? int(fabs(P) / sqrt(d2 * Q) * double(xt->n_mu)) : 0;
@@ -335,7 +342,7 @@ __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t
     wave_sync_lds();
     const uint32_t first = xn - n;
     if (uint32_t(lane) < n) {
-        const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], w.itab, xt);
+        const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], w.ai, w.ai_last, xt);
         __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         w.n_exact++;
     }
@@ -357,7 +364,7 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
     const uint32_t first = qt - n;
     const float4 e = w.qa[first + lane];
     float fm, fr;
-    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.itab, p, fm, fr);
+    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.ai, w.ai_last, p, fm, fr);
     const bool live = uint32_t(lane) < n;
     const unsigned long long live_mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
     // The lanes the estimates do not decide, from the two compares' lane
@@ -457,7 +464,7 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
 
 // Append the accepted lanes of one candidate to the queue (length qt, kept
 // wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the i index
-// within the chunk (midpoint); the other modes queue d2 (r_p^2).
+// within the task's i catalogue (midpoint); the other modes queue d2 (r_p^2).
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
                                          uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
@@ -489,10 +496,11 @@ struct JBlock {
 // Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
 // scalar loads) against the j block held one point per lane.  TAIL: some of
 // the four lie past the chunk (still inside the padded point array); their
-// tests are computed and their ballots cleared.
+// tests are computed and their ballots cleared.  irel: the chunk's first i
+// index within its catalogue (queued for the midpoint line of sight).
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL>
 __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
-                                                int jrel, const float* __restrict__ q, int64_t ib, int k,
+                                                int jrel, const float* __restrict__ q, int irel, int k,
                                                 int n_i, uint32_t qt, const PcParams& p,
                                                 const ExactTab* __restrict__ xt) {
     float a[12];
@@ -519,7 +527,7 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
     }
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(k + u), bal[u], qt, p, xt);
+        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(irel + k + u), bal[u], qt, p, xt);
     return qt;
 }
 
@@ -531,14 +539,15 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
                                             const float* __restrict__ pts, int64_t ib, int n_i,
                                             const PcParams& p, const ExactTab* __restrict__ xt) {
     ib = uniform64(ib);
+    const int irel = LOS == 1 ? int(ib - w.a0) : 0;
     uint32_t qt = w.qtail;
     int k = 0;
     for (; k + 4 <= n_i; k += 4)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), ib, k,
-                                                              n_i, qt, p, xt);
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), irel,
+                                                              k, n_i, qt, p, xt);
     if (k < n_i)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), ib, k,
-                                                             n_i, qt, p, xt);
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), irel,
+                                                             k, n_i, qt, p, xt);
     w.qtail = qt;
 }
 
@@ -546,20 +555,21 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
 // registers this spills outside the inner loops.
 template <int LOS, bool UNIFORM, bool HAS_EMIN>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
-    const float* __restrict__ pts, const int64_t* __restrict__ cs, const int2* __restrict__ tasks,
-    const int32_t* __restrict__ order, const int4* __restrict__ sten, const ExactTab* __restrict__ xt,
-    const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
+    const float* __restrict__ pts, const float* __restrict__ apts, const int64_t* __restrict__ cs,
+    const int2* __restrict__ tasks, const int32_t* __restrict__ order, const int4* __restrict__ sten,
+    const ExactTab* __restrict__ xt, const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
     unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
-    // LDS: [histogram, hist_stride words][control, 4 words][midpoint i table,
-    // 64 x 3 words][one queue of kQ entries per wave][one integer-rule queue
-    // of kX entries per wave]
+    // LDS: [histogram, hist_stride words][control, 4 words][one queue of kQ
+    // entries per wave][one integer-rule queue of kX entries per wave]
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
     unsigned* ctl = reinterpret_cast<unsigned*>(smem) + p.hist_stride;
     WaveState w;
     w.hist = reinterpret_cast<unsigned*>(smem);
-    w.itab = reinterpret_cast<int*>(ctl + 4);
+    w.ai = apts;
+    w.ai_last = 0;
+    w.a0 = 0;
     w.qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
     w.qa = reinterpret_cast<float4*>(smem + w.qbyte);
     w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kX;
@@ -610,6 +620,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
             }
             w.since_flush = 0;
             cur_task = task;
+            if (LOS == 1) {
+                // entries queued from here on hold i indices within the new
+                // task's i catalogue (both queues were binned above)
+                const int64_t cat0 = int64_t(tasks[task].x) * p.ncell * p.nsub;
+                const int64_t a0 = uniform64(cs[cat0]);
+                const int64_t a1 = uniform64(cs[cat0 + p.ncell * p.nsub]);
+                w.a0 = a0;
+                w.ai = apts + 3 * a0;
+                w.ai_last = uint32_t(max(a1 - a0, int64_t(1)) - 1);
+            }
         }
         unsigned long long* const dst = counts + int64_t(task) * p.nbins;
         const int2 tk = tasks[task];
@@ -649,18 +669,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         bhz = fmaxf(bhz, zi);
                     }
                 }
-                if (LOS == 1) {
-                    // the block's i table (chunks of at most 64 points here):
-                    // every wave has binned the entries that refer to the last one
-                    __syncthreads();
-                    if (wid == 0 && lane < n_i) {
-                        const int64_t gi = ib + lane;
-                        w.itab[3 * lane] = int(pts[3 * gi]) + oix;
-                        w.itab[3 * lane + 1] = int(pts[3 * gi + 1]) + oiy;
-                        w.itab[3 * lane + 2] = int(pts[3 * gi + 2]) + oiz;
-                    }
-                    __syncthreads();
-                }
                 for (int o = 32; o > 0; o >>= 1) {
                     blx = fminf(blx, __shfl_xor(blx, o));
                     bly = fminf(bly, __shfl_xor(bly, o));
@@ -685,7 +693,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         zj = pts[3 * jb_pend.idx + 2] + jb_pend.oz;
                     }
                     // self block: j index relative to the chunk start (pairs i < j
-                    // only; i indices within the chunk are below 64, so clamping
+                    // only; i indices within the chunk are below 256, so clamping
                     // large offsets keeps every comparison)
                     const int jrel = (vj && jb_pend.self) ? int(min(jb_pend.idx - ib, int64_t(INT_MAX))) : INT_MAX;
                     const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
@@ -780,8 +788,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     }
                 }
                 if (fill > 0) process(fill);
-                // midpoint entries refer to this chunk's i table: bin them before it changes
-                if (LOS == 1) drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
             }
         }
     }
@@ -799,8 +805,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     }
 }
 
-typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_t*, const int4*, const ExactTab*,
-                         const int32_t*, unsigned long long*, unsigned long long*, unsigned*, PcParams);
+typedef void (*PcKernel)(const float*, const float*, const int64_t*, const int2*, const int32_t*, const int4*,
+                         const ExactTab*, const int32_t*, unsigned long long*, unsigned long long*, unsigned*,
+                         PcParams);
 
 static PcKernel pick_kernel(int los, bool uniform, bool has_emin) {
     static const PcKernel tab[3][2][2] = {
@@ -897,14 +904,14 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.nmu4 = uint32_t(4 * n_mu);
     p.hist_stride = (p.nbins + 1 + 3) & ~3;  // + the discard slot
     const bool mid = b->los == LC_LOS_MID;
-    const int max_chunk = mid ? 64 : 256;  // midpoint: the i table holds 64 points
+    const int max_chunk = 256;
     // default: a whole cell per gather of its j points (fewer, larger chunks
     // cost a few more candidate tests but gather j points less often)
     const int chunk = tune && tune->chunk > 0 ? tune->chunk : max_chunk;
     if (chunk > max_chunk || chunk % 4 != 0)
         return fail(LC_ERR_INVALID, "chunk = %d, must be a multiple of 4 in [4, %d]", chunk, max_chunk);
     p.chunk = chunk;
-    p.queue_byte0 = (p.hist_stride * 4 + 16 + (mid ? 64 * 12 : 0) + 15) & ~15;
+    p.queue_byte0 = (p.hist_stride * 4 + 16 + 15) & ~15;
     const int64_t e0 = b->r_edges[0];
     const int64_t de = int64_t(b->r_edges[1]) - b->r_edges[0];
     bool uniform = true;
@@ -923,8 +930,13 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     // v_rsq_f32 is within 1 ulp = 2u):
     //   d2 (float32 sum of exact squares): 3u
     //   mu estimate |s_z| rsq(d2) n_mu - eps_m: 1.5u (from d2) + 2u + a product
-    //     and an fma 2u -> 5.5u n_mu absolute; midpoint: p and q conversions,
-    //     rsq(q), one more product -> 10u n_mu; (r_p, pi): the exact |s_z|
+    //     and an fma 2u -> 5.5u n_mu absolute; midpoint, all in float32:
+    //     l = fma(2, x_i, s) rounds once (u relative per component), so
+    //     |fl(s.l) - s.l| <= (3u + u)|s||l| (three roundings of the dot
+    //     product, Cauchy-Schwarz) = 4u of mu; q = fl(l.l) within 5u, so
+    //     rsq(q) within 2.5u + 2u; rsq(d2) within 3.5u; two products 2u:
+    //     |p| rsq(d2) rsq(q) = mu +- (4u + 10u mu) -> 14u, plus the fma u,
+    //     so 15u n_mu, taken as 16u n_mu; (r_p, pi): the exact |s_z|
     //     times a rounded n_pi / pi_max in one fma -> 2u n_pi (r_p^2, a sum of
     //     two exact squares, is within the 3u of d2)
     //   r estimate d2 rsq(d2): 1.5u + 2u + 1u = 4.5u of r; t = r/de - (e0/de +
@@ -933,7 +945,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     // The margins are 4x these bounds; pairs closer to an edge take the
     // integer rule.
     const double u = std::ldexp(1.0, -24);
-    const double em = (mid ? 10.0 : 5.5) * u * n_mu;
+    const double em = (mid ? 16.0 : 5.5) * u * n_mu;
     const float eps_m = f32_up(std::max(4.0 * em, std::ldexp(1.0, -22)));
     const double er = u * ((5.5 * double(rmax) + double(e0)) / double(de) + double(n_r) + 1.0);
     // plus the distance of an accepted pair outside [e_0, e_n) from the edge:
@@ -1098,11 +1110,12 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
         for (int t = 0; t < pl.n_tasks; t++) {
             p.single_task = t;
             hipLaunchKernelGGL(pl.kern, dim3(pl.task_blocks[t]), dim3(pl.threads), pl.lds, s, cells->pts,
-                               cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q + kXcd * t, p);
+                               cells->apts, cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st,
+                               d_q + kXcd * t, p);
         }
     } else {
-        hipLaunchKernelGGL(pl.kern, dim3(pl.blocks), dim3(pl.threads), pl.lds, s, cells->pts, cells->cs,
-                           d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q, pl.p);
+        hipLaunchKernelGGL(pl.kern, dim3(pl.blocks), dim3(pl.threads), pl.lds, s, cells->pts, cells->apts,
+                           cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q, pl.p);
     }
 }
 
@@ -1192,6 +1205,8 @@ extern "C" lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* t
         return fail(LC_ERR_INVALID, "mode = %d is not LC_PERSISTENT or LC_PER_TASK (| flags)", mode);
     if (b->periodic != cells->g.periodic || (b->periodic && b->box_units != cells->g.box))
         return fail(LC_ERR_INVALID, "binning geometry differs from the mesh's");
+    if (b->los == LC_LOS_MID && !cells->apts)
+        return fail(LC_ERR_INVALID, "the midpoint line of sight needs a mesh built with the midpoint binning");
     for (int32_t t = 0; t < n_tasks; t++)
         if (tasks[t].cat_a < 0 || tasks[t].cat_a >= cells->n_cat || tasks[t].cat_b < 0 ||
             tasks[t].cat_b >= cells->n_cat)

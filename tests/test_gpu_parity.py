@@ -306,6 +306,50 @@ def test_wedge_midpoint_bit_exact(torch, oracle_mod, lcmod):
             assert np.array_equal(gpu[t], ref), (cell_mpc, t)
 
 
+def test_wedge_midpoint_chunks_and_exact_mode(torch, oracle_mod, lcmod):
+    """Midpoint line of sight: i chunks of 4 to 256 points (queued pairs
+    keep their i index across chunks), the integer rule alone, and per-task
+    launches all give the oracle's counts."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    wl = dataclasses.replace(mockgen.WORKLOADS["c4"], n_mock=2, n_mean=9000.0, n_parents=300,
+                             n_subsets=2, subset_size=9000)
+    cats = mockgen.make_catalogues(wl)
+    pl = Pipeline(cats)
+    pl.build_cells(int(150.0 * mockgen.UNITS_PER_MPC), 2)
+    refs = [oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units, wl.n_mu, 0,
+                                   "mid") for a, b in pl.tasks]
+    runs = [(lcmod.LC_PERSISTENT, dict(chunk=256)), (lcmod.LC_PERSISTENT, dict(chunk=132, waves_per_block=16)),
+            (lcmod.LC_PERSISTENT, dict(chunk=4)), (lcmod.LC_PERSISTENT | lcmod.LC_FORCE_EXACT, None),
+            (lcmod.LC_PER_TASK, dict(chunk=256))]
+    for mode, tune in runs:
+        _say("[wedge] mode", mode, "tune", tune)
+        pl.count(mode, tune)
+        torch.cuda.synchronize()
+        gpu = pl.counts_host()
+        for t in range(len(pl.tasks)):
+            assert np.array_equal(gpu[t], refs[t]), (mode, tune, t)
+        st = pl.stats_host()
+        if mode & lcmod.LC_FORCE_EXACT:
+            # every pair phase A accepts takes the integer rule
+            assert st["exact_fallback"] >= st["binned"] > 0
+
+
+def test_midpoint_count_needs_midpoint_mesh(torch, lcmod):
+    """A mesh built for the plane-parallel binning has no absolute
+    coordinates: counting it with the midpoint binning is refused."""
+    r = np.random.default_rng(5)
+    xyz = torch.from_numpy(r.integers(1000, 200000, size=(3, 500)).astype(np.int32)).cuda()
+    off = np.array([0, 500], dtype=np.int64)
+    bz = lcmod.Binning([0, 10000, 20000], 5, False, 0, lcmod.LC_LOS_Z)
+    bm = lcmod.Binning([0, 10000, 20000], 5, False, 0, lcmod.LC_LOS_MID)
+    cells = lcmod.lc_build_cells(xyz, off, bz, 0, 0)
+    counts = torch.zeros((1, 2, 5), dtype=torch.int64, device="cuda")
+    with pytest.raises(lcmod.LcError) as ei:
+        lcmod.lc_pair_count_batch(cells, [(0, 0)], bm, counts, lcmod.LC_PERSISTENT, None)
+    assert ei.value.status == lcmod.LC_ERR_INVALID
+    cells.close()
+
+
 def test_slab_open_geometry_bit_exact(torch, oracle_mod, lcmod):
     """The paper's slab shape (open 1500 x 1500 x 300 Mpc/h, z line of sight,
     200 x 100 bins: an 80 KB block histogram) at a density the oracle counts
@@ -677,7 +721,7 @@ def _random_config(r):
     pi_max = int(r.integers(1, max(2, min(reach, span // 3)))) if los == "rppi" else 0
     cell = int(r.integers(0, 2)) * int(r.integers(max(1, edges[-1] // 4), max(2, edges[-1] + 1)))
     sub = [0, 1, 2, 4][int(r.integers(0, 4))]
-    tune = dict(chunk=4 * int(r.integers(1, 17 if los == "mid" else 65)),
+    tune = dict(chunk=4 * int(r.integers(1, 65)),
                 waves_per_block=[0, 1, 2, 4, 8, 16][int(r.integers(0, 6))],
                 cells_per_item=int(r.integers(0, 5)))
     return dict(periodic=periodic, los=los, L=L, lo=lo, span=span, edges=edges, n_mu=n_mu, pi_max=pi_max,
