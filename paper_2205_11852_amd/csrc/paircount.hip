@@ -220,9 +220,9 @@ struct WaveState {
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
-    const float* ai;      // midpoint: absolute coordinates of the task's i catalogue (wave-uniform)
-    uint32_t ai_last;     // midpoint: that catalogue's size - 1 (clamp of queued i indices)
-    int64_t a0;           // midpoint: global index of the catalogue's first point
+    const float* ai;      // midpoint: absolute coordinates of the task's j catalogue (wave-uniform)
+    uint32_t ai_last;     // midpoint: byte offset of that catalogue's last point (clamp of queued offsets)
+    int64_t b0;           // midpoint: global index of the catalogue's first point
     float4* xa;           // this wave's queue of pairs for the integer rule, entries [0, xn)
     uint32_t xn;          // wave-uniform
     uint32_t qtail;       // wave-uniform
@@ -270,21 +270,22 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         rs = __builtin_amdgcn_rsqf(d2f);
         u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
-        // l = x_i + x_j = 2 x_i + s from the i point's absolute coordinates;
-        // e.w holds its index within the task's i catalogue, clamped so that
-        // a lane past the drained entries (masked by the caller) reads inside
-        // the catalogue.  l, p = s.l and q = l.l in float32, within the error
-        // bound that make_plan's mu margin covers.
-        const uint32_t il = min(uint32_t(__float_as_int(e.w)), ai_last);
-        const float* xi = ai + il * 3u;
-        const float lx = fmaf(2.0f, xi[0], e.x);
-        const float ly = fmaf(2.0f, xi[1], e.y);
-        const float lz = fmaf(2.0f, xi[2], e.z);
+        // l = x_i + x_j = 2 x_j - s from the j point's absolute coordinates;
+        // e.w holds their byte offset in the task's j catalogue, clamped so
+        // that a lane past the drained entries (masked by the caller) reads
+        // inside the catalogue.  l, p = s.l and q = l.l in float32, within
+        // the error bound that make_plan's mu margin covers.  d2 = 0 or
+        // q = 0 give an infinite rsq and a NaN estimate, which fails.
+        const uint32_t off = min(uint32_t(__float_as_int(e.w)), ai_last);
+        const float* xj = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ai) + off);
+        const float lx = fmaf(2.0f, xj[0], -e.x);
+        const float ly = fmaf(2.0f, xj[1], -e.y);
+        const float lz = fmaf(2.0f, xj[2], -e.z);
         const float P = fmaf(e.x, lx, fmaf(e.y, ly, e.z * lz));
         const float Q = fmaf(lx, lx, fmaf(ly, ly, lz * lz));
-        d2f = fmaxf(fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z)), 1.0f);
+        d2f = fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z));
         rs = __builtin_amdgcn_rsqf(d2f);
-        u = fmaf(fabsf(P) * rs * __builtin_amdgcn_rsqf(fmaxf(Q, 1.0f)), p.nmuf, -p.mu_shift);
+        u = fmaf(fabsf(P) * (rs * p.nmuf), __builtin_amdgcn_rsqf(Q), -p.mu_shift);
     }
     // |mu| n_mu <= n_mu exactly; an estimate within eps_m of n_mu (mu near 1)
     // fails the test, so m < n_mu whenever the pair is kept
@@ -322,11 +323,11 @@ __device__ __forceinline__ int exact_entry(const float4 e, const float* __restri
         return exact_bin_z<UNIFORM>(x, y, z, k_est, m_est, xt);
     }
     // exact: absolute coordinates and separations are integers, l below 2^26
-    const uint32_t il = min(uint32_t(__float_as_int(e.w)), ai_last);
-    const float* xi = ai + il * 3u;
-    const double lx = 2.0 * double(xi[0]) + x;
-    const double ly = 2.0 * double(xi[1]) + y;
-    const double lz = 2.0 * double(xi[2]) + z;
+    const uint32_t off = min(uint32_t(__float_as_int(e.w)), ai_last);
+    const float* xj = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ai) + off);
+    const double lx = 2.0 * double(xj[0]) - x;
+    const double ly = 2.0 * double(xj[1]) - y;
+    const double lz = 2.0 * double(xj[2]) - z;
     const double P = fma(x, lx, fma(y, ly, z * lz));
     const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
     const int m_est = (d2 > 0.0 && Q > 0.0) ? int(fabs(P) / sqrt(d2 * Q) * double(xt->n_mu)) : 0;
@@ -463,8 +464,9 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
 }
 
 // Append the accepted lanes of one candidate to the queue (length qt, kept
-// wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the i index
-// within the task's i catalogue (midpoint); the other modes queue d2 (r_p^2).
+// wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the j point's
+// byte offset in the task's j catalogue (midpoint); the other modes queue d2
+// (r_p^2).
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
                                          uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
@@ -496,11 +498,11 @@ struct JBlock {
 // Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
 // scalar loads) against the j block held one point per lane.  TAIL: some of
 // the four lie past the chunk (still inside the padded point array); their
-// tests are computed and their ballots cleared.  irel: the chunk's first i
-// index within its catalogue (queued for the midpoint line of sight).
+// tests are computed and their ballots cleared.  jw: this lane's j point as
+// queued for the midpoint line of sight (its byte offset, as float bits).
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL>
 __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
-                                                int jrel, const float* __restrict__ q, int irel, int k,
+                                                int jrel, const float* __restrict__ q, float jw, int k,
                                                 int n_i, uint32_t qt, const PcParams& p,
                                                 const ExactTab* __restrict__ xt) {
     float a[12];
@@ -527,7 +529,7 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
     }
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], __int_as_float(irel + k + u), bal[u], qt, p, xt);
+        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], jw, bal[u], qt, p, xt);
     return qt;
 }
 
@@ -536,17 +538,16 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
 // chunk sweeps them.
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF>
 __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int jrel,
-                                            const float* __restrict__ pts, int64_t ib, int n_i,
+                                            float jw, const float* __restrict__ pts, int64_t ib, int n_i,
                                             const PcParams& p, const ExactTab* __restrict__ xt) {
     ib = uniform64(ib);
-    const int irel = LOS == 1 ? int(ib - w.a0) : 0;
     uint32_t qt = w.qtail;
     int k = 0;
     for (; k + 4 <= n_i; k += 4)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), irel,
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
                                                               k, n_i, qt, p, xt);
     if (k < n_i)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), irel,
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
                                                              k, n_i, qt, p, xt);
     w.qtail = qt;
 }
@@ -569,7 +570,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     w.hist = reinterpret_cast<unsigned*>(smem);
     w.ai = apts;
     w.ai_last = 0;
-    w.a0 = 0;
+    w.b0 = 0;
     w.qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
     w.qa = reinterpret_cast<float4*>(smem + w.qbyte);
     w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kX;
@@ -621,14 +622,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
             w.since_flush = 0;
             cur_task = task;
             if (LOS == 1) {
-                // entries queued from here on hold i indices within the new
-                // task's i catalogue (both queues were binned above)
-                const int64_t cat0 = int64_t(tasks[task].x) * p.ncell * p.nsub;
-                const int64_t a0 = uniform64(cs[cat0]);
-                const int64_t a1 = uniform64(cs[cat0 + p.ncell * p.nsub]);
-                w.a0 = a0;
-                w.ai = apts + 3 * a0;
-                w.ai_last = uint32_t(max(a1 - a0, int64_t(1)) - 1);
+                // entries queued from here on hold byte offsets in the new
+                // task's j catalogue (both queues were binned above)
+                const int64_t cat0 = int64_t(tasks[task].y) * p.ncell * p.nsub;
+                const int64_t b0 = uniform64(cs[cat0]);
+                const int64_t b1 = uniform64(cs[cat0 + p.ncell * p.nsub]);
+                w.b0 = b0;
+                w.ai = apts + 3 * b0;
+                w.ai_last = uint32_t(max(b1 - b0, int64_t(1)) - 1) * 12u;
             }
         }
         unsigned long long* const dst = counts + int64_t(task) * p.nbins;
@@ -696,6 +697,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     // only; i indices within the chunk are below 256, so clamping
                     // large offsets keeps every comparison)
                     const int jrel = (vj && jb_pend.self) ? int(min(jb_pend.idx - ib, int64_t(INT_MAX))) : INT_MAX;
+                    // midpoint: the j point's byte offset in its catalogue's
+                    // absolute coordinates (any value on lanes past nfill,
+                    // whose pairs are never accepted)
+                    const float jw = LOS == 1 ? __int_as_float(int(uint32_t(jb_pend.idx - w.b0) * 12u)) : 0.0f;
                     const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
                     w.n_cand += nc;
                     // keep this wave's share of the bound on every bin (nc <= 2^14)
@@ -703,10 +708,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
                     w.since_flush += uint32_t(nc);
                     if (__builtin_amdgcn_ballot_w64(vj && jb_pend.self))
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, pts, ib, n_i, p,
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, jw, pts, ib, n_i, p,
                                                                   xt);
                     else
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, pts, ib, n_i, p,
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, jw, pts, ib, n_i, p,
                                                                    xt);
                 };
                 // the block's waves share the stencil offsets of the chunk
@@ -931,7 +936,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     //   d2 (float32 sum of exact squares): 3u
     //   mu estimate |s_z| rsq(d2) n_mu - eps_m: 1.5u (from d2) + 2u + a product
     //     and an fma 2u -> 5.5u n_mu absolute; midpoint, all in float32:
-    //     l = fma(2, x_i, s) rounds once (u relative per component), so
+    //     l = fma(2, x_j, -s) rounds once (u relative per component), so
     //     |fl(s.l) - s.l| <= (3u + u)|s||l| (three roundings of the dot
     //     product, Cauchy-Schwarz) = 4u of mu; q = fl(l.l) within 5u, so
     //     rsq(q) within 2.5u + 2u; rsq(d2) within 3.5u; two products 2u:
