@@ -118,6 +118,8 @@ typedef struct {
 lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
                          int32_t n_cat, const lc_binning* b, const lc_mesh_opts* opts,
                          void* stream, lc_cells** out);
+/* Free a mesh once no queued work uses it; also drops the pair-count graphs
+ * (LC_GRAPH) captured on it.  NULL is ignored. */
 void lc_free_cells(lc_cells* cells);
 
 /* Mesh facts (HOST): grid cells per axis, cell side in units, points. */

@@ -297,6 +297,7 @@ static void free_cells_mem(lc_cells* c) {
 
 extern "C" void lc_free_cells(lc_cells* cells) {
     if (!cells) return;
+    forget_graphs(cells);
     free_cells_mem(cells);
     delete cells;
 }

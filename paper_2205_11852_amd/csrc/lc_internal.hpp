@@ -168,5 +168,7 @@ int64_t mesh_reach(const lc_binning* b);
 
 // Drop the cached pair-count graphs and autotuning results.
 void release_graphs();
+// Drop the cached graphs captured on one mesh (called when it is freed).
+void forget_graphs(const lc_cells* cells);
 void release_tuning();
 }  // namespace lc

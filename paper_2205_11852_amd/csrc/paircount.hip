@@ -1124,11 +1124,14 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
     }
 }
 
-// Graph cache: captured launch sequences keyed by everything they bake in.
+// Graph cache: captured launch sequences keyed by everything they bake in,
+// the mesh's device buffers included.  lc_free_cells drops the entries of
+// the mesh it frees (forget_graphs), so no entry outlives its buffers.
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     void* dev = nullptr;  // owned copy of the staged block
+    const lc_cells* cells = nullptr;
 };
 static std::mutex g_graph_mu;
 static std::map<std::string, GraphEntry> g_graphs;
@@ -1139,6 +1142,9 @@ static std::string graph_key(const Plan& pl, const lc_cells* cells, uint64_t* co
     auto add = [&](const void* p, size_t n) { k.append(reinterpret_cast<const char*>(p), n); };
     add(&device, sizeof device);
     add(&cells, sizeof cells);
+    add(&cells->pts, sizeof cells->pts);
+    add(&cells->apts, sizeof cells->apts);
+    add(&cells->cs, sizeof cells->cs);
     add(&counts, sizeof counts);
     add(&stats, sizeof stats);
     add(&pl.mode, sizeof pl.mode);
@@ -1156,6 +1162,7 @@ static lc_status run_graph(const Plan& pl, const lc_cells* cells, uint64_t* coun
     auto it = g_graphs.find(key);
     if (it == g_graphs.end()) {
         GraphEntry ge;
+        ge.cells = cells;
         LC_TRY_HIP(hipMalloc(&ge.dev, pl.blob.size()));
         LC_TRY_HIP(hipMemcpy(ge.dev, pl.blob.data(), pl.blob.size(), hipMemcpyHostToDevice));
         hipStream_t cap;
@@ -1181,14 +1188,28 @@ static lc_status run_graph(const Plan& pl, const lc_cells* cells, uint64_t* coun
     return LC_OK;
 }
 
+static void destroy_graph(GraphEntry& ge) {
+    if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+    if (ge.graph) (void)hipGraphDestroy(ge.graph);
+    if (ge.dev) (void)hipFree(ge.dev);
+}
+
 void release_graphs() {
     std::lock_guard<std::mutex> lk(g_graph_mu);
-    for (auto& kv : g_graphs) {
-        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-        if (kv.second.graph) (void)hipGraphDestroy(kv.second.graph);
-        if (kv.second.dev) (void)hipFree(kv.second.dev);
-    }
+    for (auto& kv : g_graphs) destroy_graph(kv.second);
     g_graphs.clear();
+}
+
+void forget_graphs(const lc_cells* cells) {
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto it = g_graphs.begin(); it != g_graphs.end();) {
+        if (it->second.cells == cells) {
+            destroy_graph(it->second);
+            it = g_graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
 }
 
 }  // namespace lc
