@@ -145,7 +145,9 @@ typedef struct { int32_t cat_a, cat_b; } lc_task;
 /* lc_pair_count_batch modes */
 #define LC_PERSISTENT   0   /* one persistent launch over a work queue of (task, cell) tiles */
 #define LC_PER_TASK     1   /* baseline: one launch per task, sized to that task */
-#define LC_GRAPH        2   /* flag: capture the launch sequence in a hipGraph, cache, replay */
+#define LC_GRAPH        2   /* flag: capture the launch sequence in a hipGraph, cache, replay.
+                                 Replays of one cached configuration share its work-queue
+                                 counters: they must not overlap (one stream, or ordered) */
 #define LC_FORCE_EXACT  4   /* flag (testing): bin every pair with the integer rule only */
 
 /* Tuning knobs; NULL or 0 fields = library defaults. */
