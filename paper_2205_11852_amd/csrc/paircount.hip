@@ -235,6 +235,13 @@ struct WaveState {
 extern __shared__ __align__(16) unsigned char smem[];
 __device__ __forceinline__ unsigned char* smem_base() { return smem; }
 
+// The LDS word at byte offset `off` of the dynamic block, addressed as the
+// plain 32-bit LDS address `off`: the pair-count kernel has no static LDS
+// (make_plan checks this), so its dynamic block starts at LDS address 0.
+// A histogram slot k 4 n_mu + 4 m then costs one 24-bit multiply-add.
+typedef __attribute__((address_space(3))) unsigned lds_u32_t;
+__device__ __forceinline__ lds_u32_t* lds_u32_at(uint32_t off) { return (lds_u32_t*)(__UINTPTR_TYPE__)off; }
+
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -377,8 +384,7 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
         live_mask & ~(__builtin_amdgcn_fcmpf(fm, p.ok_m, 4) & __builtin_amdgcn_fcmpf(fr, p.ok_r, 4));
     const bool ok = (fm < p.ok_m) && (fr < p.ok_r);
     if (ok && live)
-        __hip_atomic_fetch_add(reinterpret_cast<unsigned*>(reinterpret_cast<unsigned char*>(w.hist) + addr), 1u,
-                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(lds_u32_at(addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (xb) {
         uint32_t xn = __builtin_amdgcn_readfirstlane(w.xn);
         if (live && !ok) {
@@ -967,6 +973,14 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     if (mode & LC_FORCE_EXACT) p.ok_r = -1.0f;
     const bool has_emin = e0 > 0;
     pl.kern = pick_kernel(mid ? 1 : rppi ? 2 : 0, uniform, has_emin);
+    {
+        // the histogram is addressed from LDS address 0 (lds_u32_at): the
+        // dynamic block must not follow any static LDS
+        hipFuncAttributes fa;
+        LC_TRY_HIP(hipFuncGetAttributes(&fa, (const void*)pl.kern));
+        if (fa.sharedSizeBytes != 0)
+            return fail(LC_ERR_HIP, "pair-count kernel holds %zu bytes of static LDS", size_t(fa.sharedSizeBytes));
+    }
     pl.mode = mode;
     pl.n_tasks = n_tasks;
 
