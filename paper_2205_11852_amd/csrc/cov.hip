@@ -375,34 +375,90 @@ __global__ __launch_bounds__(256) void k_potrf_update(double* __restrict__ W, in
 }
 
 // Sum of x over the block (every thread gets the total).
+// Wave sums by butterfly shuffles, then one exchange of the per-wave sums
+// through `red` (blockDim.x a multiple of 64, at most 1024): two barriers.
 __device__ __forceinline__ double block_sum(double x, double* red) {
-    red[threadIdx.x] = x;
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    const int nw = int(blockDim.x >> 6);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
     __syncthreads();
-    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-        __syncthreads();
-    }
-    const double r = red[0];
+    double r = 0.0;
+    for (int w = 0; w < nw; w++) r += red[w];
     __syncthreads();
     return r;
 }
 
-// Householder step k (tridiagonalisation of the symmetric trailing matrix),
-// part 1: every block forms the Householder vector of row k itself (a
-// reduction over m <= n values held in L2), then p = tau A22 v, one wave per
-// row, and the block's share of v.p; block 0 also stores v, tau, d[k], e[k].
-__global__ __launch_bounds__(256) void k_hh_step1(const double* __restrict__ W, int64_t n, int64_t k,
-                                                  double* __restrict__ v, double* __restrict__ tau,
-                                                  double* __restrict__ d, double* __restrict__ e,
-                                                  double* __restrict__ pv, double* __restrict__ vp_part) {
+// Householder tridiagonalisation of the symmetric block, one launch per
+// column k = 0 .. n-3.  Step k reflects row k of the trailing matrix onto
+// alpha e1 (v = x - alpha e1, tau = 2 / v.v), forms p = tau A22 v and the
+// rank-2 update A22 -= v w^T + w v^T with w = p - K v, K = (tau/2) v.p.
+// The launch for column k applies the update of column k-1 as it goes:
+// every wave updates its own row of A22(k) while reading it (and writes it
+// back), and every block updates row k on the fly from the old row and
+// step k-1's v and p, so no block waits for another.  Indices of the
+// pending update run over A22(k-1), whose row and column 0 are row and
+// column k of W.
+struct HhPending {
+    const double* v;        // [m + 1] Householder vector of step k-1 (NULL: none pending)
+    const double* p;        // [m + 1] tau A v of step k-1
+    const double* tau;
+    const double* vp_part;  // partial sums of v.p, n1 of them
+    int64_t n1;
+};
+
+// K of the pending update: the same ordered reduction in every block.
+__device__ __forceinline__ double hh_pending_k(const HhPending& q, double* red) {
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < q.n1; i += blockDim.x) s += q.vp_part[i];
+    const double t = block_sum(s, red);
+    return q.v ? 0.5 * *q.tau * t : 0.0;
+}
+
+// element (i, j) of A22(k-1) with the pending update applied
+__device__ __forceinline__ double hh_apply(double a, const HhPending& q, double K, int64_t i, int64_t j) {
+    if (!q.v) return a;
+    const double wi = q.p[i] - K * q.v[i], wj = q.p[j] - K * q.v[j];
+    return a - (q.v[i] * wj + wi * q.v[j]);
+}
+
+// The pending update's v and w at index i (zero when none is pending).
+struct HhVW {
+    double v, w;
+};
+__device__ __forceinline__ HhVW hh_vw(const HhPending& q, double K, int64_t i) {
+    if (!q.v) return HhVW{0.0, 0.0};
+    const double v = q.v[i];
+    return HhVW{v, q.p[i] - K * v};
+}
+
+__global__ __launch_bounds__(256) void k_hh_column(double* __restrict__ W, int64_t n, int64_t k, HhPending q,
+                                                   double* __restrict__ v, double* __restrict__ tau,
+                                                   double* __restrict__ d, double* __restrict__ e,
+                                                   double* __restrict__ pv, double* __restrict__ vp_part) {
     __shared__ double red[256];
     __shared__ double wsum[4];
     const int64_t m = n - k - 1;
+    const bool pend = q.v != nullptr;
+    const double K = hh_pending_k(q, red);
+    // row k beyond the diagonal, old values; its updated value at j is
+    // x_j = row[j] - (v_0 w_{j+1} + w_0 v_{j+1}) (pending update, index 0)
     const double* row = W + k * n + k + 1;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) s += row[i] * row[i];
-    const double norm2 = block_sum(s, red);
-    const double x0 = row[0];
+    const HhVW z = hh_vw(q, K, 0);
+    auto xk = [&](int64_t j, const HhVW& c) { return pend ? row[j] - (z.v * c.w + z.w * c.v) : row[j]; };
+    // four independent partial sums per thread keep several loads in flight
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t j0 = threadIdx.x; j0 < m; j0 += 4 * int64_t(blockDim.x)) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            const int64_t j = j0 + u * int64_t(blockDim.x);
+            if (j < m) {
+                const double x = xk(j, hh_vw(q, K, j + 1));
+                s4[u] += x * x;
+            }
+        }
+    }
+    const double norm2 = block_sum((s4[0] + s4[1]) + (s4[2] + s4[3]), red);
+    const double x0 = xk(0, hh_vw(q, K, 1));
     const double nrm = sqrt(norm2);
     const double alpha = x0 > 0 ? -nrm : nrm;   // reflect x onto alpha * e1
     const double v0 = x0 - alpha;
@@ -410,62 +466,65 @@ __global__ __launch_bounds__(256) void k_hh_step1(const double* __restrict__ W, 
     const bool trivial = !(vnorm2 > 0.0) || (norm2 - x0 * x0) <= 0.0;
     const double t = trivial ? 0.0 : 2.0 / vnorm2;
     if (blockIdx.x == 0) {
-        for (int64_t i = threadIdx.x; i < m; i += blockDim.x) v[i] = trivial ? 0.0 : (i == 0 ? v0 : row[i]);
+        for (int64_t i = threadIdx.x; i < m; i += blockDim.x)
+            v[i] = trivial ? 0.0 : (i == 0 ? v0 : xk(i, hh_vw(q, K, i + 1)));
         if (threadIdx.x == 0) {
-            d[k] = W[k * n + k];
+            d[k] = hh_apply(W[k * n + k], q, K, 0, 0);
             e[k] = trivial ? x0 : alpha;
             *tau = t;
         }
     }
-    // p_r = tau sum_j A22[r][j] v_j (v_j from row k, v_0 = x0 - alpha)
+    // p_r = tau sum_j A22[r][j] v_j, one wave per row; the row is brought up
+    // to date (pending update, index r + 1) as it is read and written back
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t r = blockIdx.x * int64_t(blockDim.x >> 6) + wv;
     double vpr = 0.0;
     if (r < m) {
-        const double* ar = W + (k + 1 + r) * n + k + 1;
-        double acc = 0.0;
-        for (int64_t j = lane; j < m; j += 64) acc += ar[j] * (j == 0 ? v0 : row[j]);
+        double* ar = W + (k + 1 + r) * n + k + 1;
+        const HhVW y = hh_vw(q, K, r + 1);
+        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int64_t j0 = lane; j0 < m; j0 += 256) {
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const int64_t j = j0 + 64 * u;
+                if (j < m) {
+                    const HhVW c = hh_vw(q, K, j + 1);
+                    double a = ar[j];
+                    if (pend) {
+                        a = a - (y.v * c.w + y.w * c.v);
+                        ar[j] = a;
+                    }
+                    acc4[u] += a * (j == 0 ? v0 : xk(j, c));
+                }
+            }
+        }
+        double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
         const double p = trivial ? 0.0 : t * acc;
         if (lane == 0) pv[r] = p;
-        vpr = trivial ? 0.0 : p * (r == 0 ? v0 : row[r]);
+        vpr = trivial ? 0.0 : p * (r == 0 ? v0 : xk(r, hh_vw(q, K, r + 1)));
     }
     if (lane == 0) wsum[wv] = vpr;
     __syncthreads();
     if (threadIdx.x == 0) {
         double b = 0.0;
-        for (int q = 0; q < int(blockDim.x >> 6); q++) b += wsum[q];
+        for (int w = 0; w < int(blockDim.x >> 6); w++) b += wsum[w];
         vp_part[blockIdx.x] = b;
     }
 }
 
-// Householder step k, part 2: every block forms K = (tau/2)(v.p) from the
-// n1 partial sums (in a fixed order) and applies A22 -= v w^T + w v^T with
-// w = p - K v to its part of A22.
-__global__ __launch_bounds__(256) void k_hh_step2(double* __restrict__ W, int64_t n, int64_t k,
-                                                  const double* __restrict__ v, const double* __restrict__ tau,
-                                                  const double* __restrict__ pv, const double* __restrict__ vp_part,
-                                                  int64_t n1) {
+// The last 2 x 2 block (rows n-2, n-1 = indices 0, 1 of the pending update's
+// A22) gives the last diagonal and off-diagonal entries.  One block.
+__global__ void k_hh_tail(const double* __restrict__ W, int64_t n, HhPending q, double* __restrict__ d,
+                          double* __restrict__ e) {
     __shared__ double red[256];
-    const int64_t m = n - k - 1;
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < n1; i += blockDim.x) s += vp_part[i];
-    const double K = 0.5 * *tau * block_sum(s, red);
-    for (int64_t q = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; q < m * m;
-         q += int64_t(gridDim.x) * blockDim.x) {
-        const int64_t i = q / m, j = q % m;
-        const double wi = pv[i] - K * v[i], wj = pv[j] - K * v[j];
-        W[(k + 1 + i) * n + k + 1 + j] -= v[i] * wj + wi * v[j];
-    }
-}
-
-__global__ void k_hh_tail(const double* __restrict__ W, int64_t n, double* __restrict__ d, double* __restrict__ e) {
+    const double K = hh_pending_k(q, red);
     if (threadIdx.x != 0) return;
     if (n >= 2) {
-        d[n - 2] = W[(n - 2) * n + n - 2];
-        e[n - 2] = W[(n - 1) * n + n - 2];
+        d[n - 2] = hh_apply(W[(n - 2) * n + n - 2], q, K, 0, 0);
+        e[n - 2] = hh_apply(W[(n - 1) * n + n - 2], q, K, 1, 0);
     }
-    d[n - 1] = W[(n - 1) * n + n - 1];
+    d[n - 1] = hh_apply(W[(n - 1) * n + n - 1], q, K, n >= 2 ? 1 : 0, n >= 2 ? 1 : 0);
 }
 
 // number of eigenvalues of the tridiagonal (d, e) below x (Sturm count)
@@ -557,20 +616,22 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     DevBuf<double> Wb, auxb;
     DevBuf<CheckFlags> flb;
     LC_TRY(Wb.alloc(size_t(n * n), s));
-    const int64_t naux = 6 * n + 16;
+    const int64_t naux = 8 * n + 32;
     LC_TRY(auxb.alloc(size_t(naux), s));
     LC_TRY(flb.alloc(2, s));
     double* W = Wb.get();
     double* aux = auxb.get();
     CheckFlags* fl = flb.get();
     k_zero_flags<<<1, 64, 0, s>>>(fl, 2);
-    double* v = aux;
-    double* pv = aux + n;
-    double* d = aux + 3 * n;
-    double* e = aux + 4 * n;
-    double* tau = aux + 5 * n;
-    double* res = aux + 5 * n + 4;
-    double* vpp = aux + 5 * n + 16;     // partial sums of v.p, (n + 3)/4 of them
+    // two sets of Householder buffers: the launch for column k reads step
+    // k-1's set while it fills its own
+    double* const v[2] = {aux, aux + n};
+    double* const pv[2] = {aux + 2 * n, aux + 3 * n};
+    double* d = aux + 4 * n;
+    double* e = aux + 5 * n;
+    double* const vpp[2] = {aux + 6 * n, aux + 7 * n};  // partial sums of v.p, (n + 3)/4 each
+    double* tau = aux + 8 * n;                           // [2]
+    double* res = aux + 8 * n + 4;
     // Cholesky
     k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl);
     for (int64_t k0 = 0; k0 < n; k0 += kNB) {
@@ -585,14 +646,15 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     }
     // eigenvalues: fresh copy, tridiagonalise, bisect
     k_copy_block<<<nblocks(n * n, 256), 256, 0, s>>>(C, P, off, n, W, fl + 1);
+    HhPending q{nullptr, nullptr, nullptr, nullptr, 0};
     for (int64_t k = 0; k + 2 < n; k++) {
         const int64_t m = n - k - 1;
-        // one wave per row of p (4 per block)
-        const int64_t n1 = (m + 3) / 4;
-        k_hh_step1<<<unsigned(n1), 256, 0, s>>>(W, n, k, v, tau, d, e, pv, vpp);
-        k_hh_step2<<<nblocks(m * m, 256, 1024), 256, 0, s>>>(W, n, k, v, tau, pv, vpp, n1);
+        const int64_t n1 = (m + 3) / 4;  // one wave per row of A22 (4 per block)
+        const int c = int(k & 1);
+        k_hh_column<<<unsigned(n1), 256, 0, s>>>(W, n, k, q, v[c], tau + c, d, e, pv[c], vpp[c]);
+        q = HhPending{v[c], pv[c], tau + c, vpp[c], n1};
     }
-    k_hh_tail<<<1, 64, 0, s>>>(W, n, d, e);
+    k_hh_tail<<<1, 256, 0, s>>>(W, n, q, d, e);
     k_bisect<<<1, 256, 0, s>>>(d, e, n, fl + 1, res);
     CheckFlags hf[2];
     double hr[3];
