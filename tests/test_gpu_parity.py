@@ -333,8 +333,8 @@ def test_wedge_midpoint_bit_exact(torch, oracle_mod, lcmod):
 
 def test_wedge_midpoint_chunks_and_exact_mode(torch, oracle_mod, lcmod):
     """Midpoint line of sight: i chunks of 4 to 256 points (queued pairs
-    keep their i index across chunks), the integer rule alone, and per-task
-    launches all give the oracle's counts."""
+    keep their j offsets across chunks), the integer rule alone, per-task
+    launches and graph replays all give the oracle's counts."""
     from paper_2205_11852_amd.pipeline import Pipeline
     wl = dataclasses.replace(mockgen.WORKLOADS["c4"], n_mock=2, n_mean=9000.0, n_parents=300,
                              n_subsets=2, subset_size=9000)
@@ -345,7 +345,8 @@ def test_wedge_midpoint_chunks_and_exact_mode(torch, oracle_mod, lcmod):
                                    "mid") for a, b in pl.tasks]
     runs = [(lcmod.LC_PERSISTENT, dict(chunk=256)), (lcmod.LC_PERSISTENT, dict(chunk=132, waves_per_block=16)),
             (lcmod.LC_PERSISTENT, dict(chunk=4)), (lcmod.LC_PERSISTENT | lcmod.LC_FORCE_EXACT, None),
-            (lcmod.LC_PER_TASK, dict(chunk=256))]
+            (lcmod.LC_PER_TASK, dict(chunk=256)), (lcmod.LC_GRAPH, None), (lcmod.LC_GRAPH, None),
+            (lcmod.LC_GRAPH | lcmod.LC_PER_TASK, None)]
     for mode, tune in runs:
         _say("[wedge] mode", mode, "tune", tune)
         pl.count(mode, tune)
