@@ -431,12 +431,17 @@ __device__ __forceinline__ HhVW hh_vw(const HhPending& q, double K, int64_t i) {
     return HhVW{v, q.p[i] - K * v};
 }
 
-__global__ __launch_bounds__(256) void k_hh_column(double* __restrict__ W, int64_t n, int64_t k, HhPending q,
+constexpr int kHhRows = 4;  // rows of A22 per k_hh_column block
+
+// WAVES waves per row: 4 while the trailing matrix is large (more loads in
+// flight), 1 once it is small (the launch's fixed cost dominates)
+template <int WAVES>
+__global__ __launch_bounds__(64 * kHhRows * WAVES) void k_hh_column(double* __restrict__ W, int64_t n, int64_t k, HhPending q,
                                                    double* __restrict__ v, double* __restrict__ tau,
                                                    double* __restrict__ d, double* __restrict__ e,
                                                    double* __restrict__ pv, double* __restrict__ vp_part) {
-    __shared__ double red[256];
-    __shared__ double wsum[4];
+    __shared__ double red[kHhRows * WAVES];
+    __shared__ double wsum[kHhRows * WAVES];
     const int64_t m = n - k - 1;
     const bool pend = q.v != nullptr;
     const double K = hh_pending_k(q, red);
@@ -474,19 +479,21 @@ __global__ __launch_bounds__(256) void k_hh_column(double* __restrict__ W, int64
             *tau = t;
         }
     }
-    // p_r = tau sum_j A22[r][j] v_j, one wave per row; the row is brought up
-    // to date (pending update, index r + 1) as it is read and written back
+    // p_r = tau sum_j A22[r][j] v_j, WAVES waves per row (kHhRows rows per
+    // block) taking 64 columns in turn; the row is brought up to date
+    // (pending update, index r + 1) as it is read and written back
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r = blockIdx.x * int64_t(blockDim.x >> 6) + wv;
-    double vpr = 0.0;
+    const int64_t r = blockIdx.x * int64_t(kHhRows) + wv / WAVES;
+    const int64_t jl = int64_t(wv % WAVES) * 64 + lane;
+    double acc = 0.0;
     if (r < m) {
         double* ar = W + (k + 1 + r) * n + k + 1;
         const HhVW y = hh_vw(q, K, r + 1);
         double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t j0 = lane; j0 < m; j0 += 256) {
+        for (int64_t j0 = jl; j0 < m; j0 += 4 * 64 * WAVES) {
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const int64_t j = j0 + 64 * u;
+                const int64_t j = j0 + 64 * WAVES * u;
                 if (j < m) {
                     const HhVW c = hh_vw(q, K, j + 1);
                     double a = ar[j];
@@ -498,17 +505,22 @@ __global__ __launch_bounds__(256) void k_hh_column(double* __restrict__ W, int64
                 }
             }
         }
-        double acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+        acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-        const double p = trivial ? 0.0 : t * acc;
-        if (lane == 0) pv[r] = p;
-        vpr = trivial ? 0.0 : p * (r == 0 ? v0 : xk(r, hh_vw(q, K, r + 1)));
     }
-    if (lane == 0) wsum[wv] = vpr;
+    if (lane == 0) wsum[wv] = acc;
     __syncthreads();
     if (threadIdx.x == 0) {
         double b = 0.0;
-        for (int w = 0; w < int(blockDim.x >> 6); w++) b += wsum[w];
+        for (int i = 0; i < kHhRows; i++) {
+            const int64_t ri = blockIdx.x * int64_t(kHhRows) + i;
+            if (ri >= m) break;
+            double a = 0.0;
+            for (int w = 0; w < WAVES; w++) a += wsum[WAVES * i + w];
+            const double p = trivial ? 0.0 : t * a;
+            pv[ri] = p;
+            b += trivial ? 0.0 : p * (ri == 0 ? v0 : xk(ri, hh_vw(q, K, ri + 1)));
+        }
         vp_part[blockIdx.x] = b;
     }
 }
@@ -649,9 +661,12 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
     HhPending q{nullptr, nullptr, nullptr, nullptr, 0};
     for (int64_t k = 0; k + 2 < n; k++) {
         const int64_t m = n - k - 1;
-        const int64_t n1 = (m + 3) / 4;  // one wave per row of A22 (4 per block)
+        const int64_t n1 = (m + kHhRows - 1) / kHhRows;
         const int c = int(k & 1);
-        k_hh_column<<<unsigned(n1), 256, 0, s>>>(W, n, k, q, v[c], tau + c, d, e, pv[c], vpp[c]);
+        if (m >= 256)
+            k_hh_column<4><<<unsigned(n1), 64 * kHhRows * 4, 0, s>>>(W, n, k, q, v[c], tau + c, d, e, pv[c], vpp[c]);
+        else
+            k_hh_column<1><<<unsigned(n1), 64 * kHhRows, 0, s>>>(W, n, k, q, v[c], tau + c, d, e, pv[c], vpp[c]);
         q = HhPending{v[c], pv[c], tau + c, vpp[c], n1};
     }
     k_hh_tail<<<1, 256, 0, s>>>(W, n, q, d, e);
