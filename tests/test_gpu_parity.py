@@ -671,6 +671,29 @@ def test_covariance_general_parity(torch, oracle_mod, lcmod, m_a, m_b, n_split):
             assert rep["n_neg_eig"][blk] == int((wv < 0).sum())
 
 
+@pytest.mark.parametrize("P,n_split", [(1, 0), (2, 1), (3, 0), (4, 1), (5, 3), (258, 2), (300, 43)])
+def test_check_block_sizes(torch, oracle_mod, lcmod, P, n_split):
+    """The check's Householder and bisection on blocks of 1 to 298 rows (both
+    sides of the 256-row switch of the column kernel), against LAPACK."""
+    n_mock = 600
+    V = _synthetic_vectors(n_mock, P, 1000 + P)
+    xi = torch.from_numpy(V).cuda()
+    A, B, C = (torch.empty((P, P), dtype=torch.float64, device="cuda") for _ in range(3))
+    rep = lcmod.lc_covariance_general(xi, n_mock, P, n_split, 1.0, 2.0, 50.0, lcmod.LC_FP64, A, B, C, report=True)
+    torch.cuda.synchronize()
+    gC = C.cpu().numpy()
+    for blk, sl in enumerate((slice(0, n_split), slice(n_split, P))):
+        if sl.stop - sl.start == 0:
+            assert rep["chol_ok"][blk] == 1 and rep["n_neg_eig"][blk] == 0
+            continue
+        ref = oracle_mod.check_matrix(gC[sl, sl])
+        scale = max(abs(ref["min_eig"]), abs(ref["max_eig"]))
+        assert abs(rep["min_eig"][blk] - ref["min_eig"]) <= 1e-10 * scale, (P, n_split, blk)
+        assert abs(rep["max_eig"][blk] - ref["max_eig"]) <= 1e-10 * scale, (P, n_split, blk)
+        assert rep["n_neg_eig"][blk] == ref["n_neg_eig"], (P, n_split, blk)
+        assert rep["chol_ok"][blk] == ref["chol_ok"], (P, n_split, blk)
+
+
 def test_covariance_general_at_paper_ratios_equals_lc_covariance(c1, c1_cov, torch, lcmod):
     """With M_b = 2 M_a and the (r, mu) block split, the general call is
     lc_covariance, bit for bit."""
