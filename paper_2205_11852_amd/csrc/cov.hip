@@ -553,18 +553,33 @@ __device__ int sturm_count(const double* d, const double* e, int64_t n, double x
     return c;
 }
 
-// out: [0] min eig, [1] max eig, [2] count below 0 (as double)
-__global__ void k_bisect(const double* __restrict__ d, const double* __restrict__ e, int64_t n,
-                         const CheckFlags* fl, double* __restrict__ out) {
+// out: [0] min eig, [1] max eig, [2] count below 0 (as double).  Three
+// blocks work at once: block 0 bisects for the smallest eigenvalue, block 1
+// for the largest (kBisectThreads Sturm counts per round, one wave per
+// SIMD), block 2 counts the eigenvalues below 0.  A Sturm count is a serial
+// recurrence over the n entries; up to kBisectLds entries are first copied
+// to LDS, so each step waits on an LDS load rather than a global one.
+constexpr int kBisectThreads = 256;
+constexpr int64_t kBisectLds = 3072;  // 48 KB of LDS for d and e
+__global__ __launch_bounds__(kBisectThreads) void k_bisect(const double* __restrict__ d_g,
+                                                           const double* __restrict__ e_g, int64_t n,
+                                                           const CheckFlags* fl, double* __restrict__ out) {
     __shared__ double lo_s, hi_s, piv_s;
-    __shared__ int cnt[256];
+    __shared__ int cnt[kBisectThreads];
+    __shared__ double d_l[kBisectLds], e_l[kBisectLds];
     if (fl->nan_seen) {
-        if (threadIdx.x == 0) {
-            out[0] = out[1] = __builtin_nan("");
-            out[2] = -1.0;
-        }
+        if (threadIdx.x == 0) out[blockIdx.x] = blockIdx.x == 2 ? -1.0 : __builtin_nan("");
         return;
     }
+    const bool staged = n <= kBisectLds;
+    if (staged)
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            d_l[i] = d_g[i];
+            e_l[i] = e_g[i];
+        }
+    __syncthreads();
+    const double* d = staged ? d_l : d_g;
+    const double* e = staged ? e_l : e_g;
     double glo = 0, ghi = 0, emax2 = 0;
     if (threadIdx.x == 0) {
         glo = DBL_MAX;
@@ -584,8 +599,13 @@ __global__ void k_bisect(const double* __restrict__ d, const double* __restrict_
     }
     __syncthreads();
     const double pivmin = piv_s;
-    for (int which = 0; which < 2; which++) {
-        // which 0: smallest x with count(x) >= 1; which 1: smallest x with count(x) >= n
+    if (blockIdx.x == 2) {
+        if (threadIdx.x == 0) out[2] = double(sturm_count(d, e, n, 0.0, pivmin));
+        return;
+    }
+    {
+        // block 0: smallest x with count(x) >= 1; block 1: smallest x with count(x) >= n
+        const int which = int(blockIdx.x);
         double lo = lo_s, hi = hi_s;
         const int target = which == 0 ? 1 : int(n);
         for (int it = 0; it < 12; it++) {
@@ -609,7 +629,6 @@ __global__ void k_bisect(const double* __restrict__ d, const double* __restrict_
         }
         if (threadIdx.x == 0) out[which] = 0.5 * (lo + hi);
     }
-    if (threadIdx.x == 0) out[2] = double(sturm_count(d, e, n, 0.0, pivmin));
 }
 
 static int nblocks(int64_t n, int threads, int cap = 4096) {
@@ -670,7 +689,7 @@ static lc_status check_block(const double* C, int64_t P, int64_t off, int64_t n,
         q = HhPending{v[c], pv[c], tau + c, vpp[c], n1};
     }
     k_hh_tail<<<1, 256, 0, s>>>(W, n, q, d, e);
-    k_bisect<<<1, 256, 0, s>>>(d, e, n, fl + 1, res);
+    k_bisect<<<3, kBisectThreads, 0, s>>>(d, e, n, fl + 1, res);
     CheckFlags hf[2];
     double hr[3];
     LC_TRY_HIP(hipMemcpyAsync(hf, fl, sizeof hf, hipMemcpyDeviceToHost, s));
