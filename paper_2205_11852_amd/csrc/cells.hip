@@ -146,20 +146,24 @@ __global__ void k_zero_u32(unsigned* p, int64_t n) {
         p[i] = 0;
 }
 
-__device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, int32_t n_cat, int64_t p) {
-    // largest c with off[c] <= p (catalogues may be empty)
-    int32_t lo = 0, hi = n_cat;  // off[lo] <= p < off[hi]
-    while (hi - lo > 1) {
-        int32_t mid = (lo + hi) >> 1;
-        if (off[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    return lo;
+// Catalogue lookup: lut[b] is the last catalogue starting at or before
+// point b << kCatShift (built on the host); a point's catalogue is found
+// from there by skipping forward past catalogues that end at or before it.
+constexpr int kCatShift = 12;
+
+__device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, const int32_t* __restrict__ lut,
+                                            int64_t p) {
+    int32_t c = lut[p >> kCatShift];
+    while (off[c + 1] <= p) ++c;  // ends: p < off[n_cat]
+    return c;
 }
 
-// Cell id per point and per-cell histogram; range check for periodic boxes.
+// Cell id per point, its rank within the sub-cell (the returned value of the
+// per-cell counter), packed as id << 32 | rank (sub-cell ids are below
+// 2^31), and the per-cell histogram; range check for periodic boxes (an
+// out-of-range point gets ~0).
 __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
-                             int32_t n_cat, GridGeom g, int64_t* __restrict__ gid,
+                             const int32_t* __restrict__ lut, GridGeom g, uint64_t* __restrict__ gid,
                              unsigned* __restrict__ cnt, unsigned* __restrict__ err) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
@@ -167,7 +171,7 @@ __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const i
         if (g.periodic) {
             if (x < 0 || y < 0 || z < 0 || x >= g.box || y >= g.box || z >= g.box) {
                 atomicOr(err, 2u);
-                gid[p] = -1;
+                gid[p] = ~0ull;
                 continue;
             }
         }
@@ -177,10 +181,10 @@ __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const i
         const int32_t fz = axis_cell(z, g.lo[2], g.ext[2], g.n[2] * g.sub);
         const int32_t cx = fx / g.sub, cy = fy / g.sub, cz = fz / g.sub;
         const int32_t sid = ((fz - cz * g.sub) * g.sub + (fy - cy * g.sub)) * g.sub + (fx - cx * g.sub);
-        int32_t c = find_cat(off, n_cat, p);
-        int64_t id = (int64_t(c) * g.ncell + (int64_t(cz) * g.n[1] + cy) * g.n[0] + cx) * g.nsub + sid;
-        gid[p] = id;
-        atomicAdd(&cnt[id], 1u);
+        const int32_t c = find_cat(off, lut, p);
+        const int64_t id = (int64_t(c) * g.ncell + (int64_t(cz) * g.n[1] + cy) * g.n[0] + cx) * g.nsub + sid;
+        const unsigned rank = atomicAdd(&cnt[id], 1u);
+        gid[p] = (uint64_t(id) << 32) | rank;
     }
 }
 
@@ -253,19 +257,19 @@ __global__ void k_scan_down(const unsigned* __restrict__ cnt, int64_t n, const i
 
 __global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out[n] = *grand; }
 
-// Scatter: each point takes a slot in its cell (order inside a cell is free;
-// counts never depend on it) and is stored relative to the cell origin.
+// Scatter: each point goes to slot start + rank of its sub-cell (the order
+// inside a sub-cell is the counters' order, which no count depends on) and
+// is stored relative to its cell origin.
 // apts (midpoint meshes, else NULL) receives the same slot's absolute
 // coordinates, exact in float32 since open geometry keeps |x| < 2^24.
-__global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ gid,
-                          const int64_t* __restrict__ cs, unsigned* __restrict__ cnt, GridGeom g,
-                          float* __restrict__ pts, float* __restrict__ apts) {
+__global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint64_t* __restrict__ gid,
+                          const int64_t* __restrict__ cs, GridGeom g, float* __restrict__ pts,
+                          float* __restrict__ apts) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
-        int64_t id = gid[p];
-        if (id < 0) continue;
-        unsigned r = atomicSub(&cnt[id], 1u) - 1u;
-        const int64_t slot = cs[id] + r;
+        const uint64_t gv = gid[p];
+        if (gv == ~0ull) continue;
+        const int64_t slot = cs[int64_t(gv >> 32)] + int64_t(uint32_t(gv));
         const int32_t v[3] = {xyz[p], xyz[n + p], xyz[2 * n + p]};
         for (int a = 0; a < 3; a++) {
             const int32_t c = axis_cell(v[a], g.lo[a], g.ext[a], g.n[a]);
@@ -438,17 +442,29 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
 
     // temporaries
     int64_t* d_off = nullptr;
-    int64_t* d_gid = nullptr;
+    const int32_t* d_lut = nullptr;
+    uint64_t* d_gid = nullptr;
     unsigned* d_cnt = nullptr;
     int64_t* d_bsum = nullptr;
     const int64_t nblk = (ntot_cells + kScanTile - 1) / kScanTile;
     lc_status st = LC_OK;
     {
+        // catalogue of every (1 << kCatShift)-th point: the last catalogue
+        // starting at or before it
+        std::vector<int32_t> lut(size_t(n_total >> kCatShift) + 1);
+        int32_t c = 0;
+        for (size_t bi = 0; bi < lut.size(); bi++) {
+            const int64_t p0 = int64_t(bi) << kCatShift;
+            while (c + 1 < n_cat && cat_offsets[c + 1] <= p0) ++c;
+            lut[bi] = c;
+        }
         Stager stg(ctx);
         stg.push(cat_offsets, sizeof(int64_t) * (n_cat + 1));
+        const size_t lut_off = stg.push(lut.data(), sizeof(int32_t) * lut.size());
         st = stg.commit(s, (void**)&d_off);
+        if (st == LC_OK) d_lut = reinterpret_cast<const int32_t*>(reinterpret_cast<unsigned char*>(d_off) + lut_off);
     }
-    if (st == LC_OK) st = dev_alloc((void**)&d_gid, sizeof(int64_t) * std::max<int64_t>(n_total, 1), s);
+    if (st == LC_OK) st = dev_alloc((void**)&d_gid, sizeof(uint64_t) * std::max<int64_t>(n_total, 1), s);
     if (st == LC_OK) st = dev_alloc((void**)&d_cnt, sizeof(unsigned) * ntot_cells, s);
     if (st == LC_OK) st = dev_alloc((void**)&d_bsum, sizeof(int64_t) * (nblk + 1), s);
     if (st != LC_OK) {
@@ -464,15 +480,15 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(cells->pts) + 3 * n_total, 12);
     if (mid) k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(cells->apts) + 3 * n_total, 12);
     if (n_total > 0)
-        k_cell_count<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_off, n_cat, g,
+        k_cell_count<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_off, d_lut, g,
                                                                        d_gid, d_cnt, d_err);
     k_scan_reduce<<<nblk, kScanThreads, 0, s>>>(d_cnt, ntot_cells, d_bsum);
     k_scan_top<<<1, kScanThreads, 0, s>>>(d_bsum, nblk, d_bsum + nblk);
     k_scan_down<<<nblk, kScanThreads, 0, s>>>(d_cnt, ntot_cells, d_bsum, cells->cs);
     k_scan_last<<<1, 1, 0, s>>>(cells->cs, ntot_cells, d_bsum + nblk);
     if (n_total > 0)
-        k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, d_cnt,
-                                                                    g, cells->pts, cells->apts);
+        k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, g,
+                                                                    cells->pts, cells->apts);
     unsigned herr = 0;
     hipError_t e = hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s);
     dev_free(d_off, s);
