@@ -6,7 +6,8 @@ checks sampled tasks one by one (brute force, bit for bit), the data vector
 of one mock (float64, 1e-12), and properties that hold at any size: the
 counts do not depend on the tiling, and per-task launches give the same
 counts.  The covariance stage runs at the full data-vector sizes on seeded
-synthetic vectors.  Smaller workloads of the other configurations' shapes
+synthetic vectors, and on the 5000 measured vectors of the
+covariance-precision workload against the float64 oracle.  Smaller workloads of the other configurations' shapes
 (100 mu bins with per-mock randoms) are compared task by task.
 """
 import dataclasses
@@ -169,6 +170,62 @@ def test_slab_counts_independent_of_tiling(slab, torch):
     torch.cuda.synchronize()
     assert np.array_equal(pl.counts_host(), slab["counts"])
     pl.build_cells()
+
+
+@pytest.fixture(scope="module")
+def c5(torch, lcmod):
+    """The covariance-precision workload at full size: 5000 mocks of
+    Poisson(5e4) points, 40 x 50 bins, counted in one persistent launch with
+    the library defaults; the data vectors (P = 2120) stay on the host."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    _say("[c5] generating 5000 mocks")
+    cats = mockgen.make_catalogues(mockgen.WORKLOADS["c5"], progress=_say)
+    pl = Pipeline(cats)
+    pl.build_cells()
+    pl.count()
+    pl.xi_multipoles()
+    torch.cuda.synchronize()
+    _say("[c5] counted %d tasks" % len(pl.tasks))
+    return dict(pl=pl, cats=cats, counts=pl.counts_host().copy(), xi=pl.xi.cpu().numpy())
+
+
+def test_c5_sampled_tasks_and_data_vector(c5, oracle_mod):
+    """Every task of mock 0 and the last mock's DD, brute force, bit for bit;
+    mock 0's three estimates and their multipoles within 1e-12."""
+    pl, cats = c5["pl"], c5["cats"]
+    wl = cats.wl
+    ref = {}
+    for t in list(pl.est[0]) + [pl.est[-1][0]]:
+        a, b = pl.tasks[t]
+        _say("[c5] oracle task", int(t), (int(a), int(b)))
+        ref[int(t)] = oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), wl.r_edges_units,
+                                             wl.n_mu, wl.box_units, wl.los)
+        assert np.array_equal(c5["counts"][t], ref[int(t)]), int(t)
+    e = pl.est[0]
+    D, R1, R2 = pl.tasks[e[0]][0], pl.tasks[e[1]][1], pl.tasks[e[2]][1]
+    V = oracle_mod.mock_vectors(*(ref[int(t)] for t in e), pl.sizes[D], pl.sizes[R1], pl.sizes[R2])
+    g = c5["xi"][0]
+    assert np.array_equal(np.isnan(g), np.isnan(V))
+    ok = np.isfinite(V)
+    nb = pl.binning.n_r * pl.binning.n_mu
+    assert np.allclose(g[:, :nb][ok[:, :nb]], V[:, :nb][ok[:, :nb]], rtol=1e-12, atol=0)
+
+
+def test_c5_covariance_precision_against_oracle(c5, oracle_mod, lcmod, torch):
+    """The 5000 measured data vectors (P = 2120): the float32-MFMA products
+    give A, B and C^LC(50) within 1e-5 (relative Frobenius) of the float64
+    oracle's, and the float64 path within 1e-12."""
+    pl = c5["pl"]
+    V = c5["xi"]
+    rA, rB, rC, _, _ = oracle_mod.lc_from_vectors(V, 1, 50.0)
+    for prec, tol in ((lcmod.LC_FP32_MFMA, 1e-5), (lcmod.LC_FP64, 1e-12)):
+        _say("[c5] covariance, precision", prec)
+        pl.covariance(prec, report=False, M=50.0)
+        torch.cuda.synchronize()
+        gA, gB, gC = (t.cpu().numpy() for t in (pl.A, pl.B, pl.C))
+        errs = [_rel_frob(x, y) for x, y in ((gA, rA), (gB, rB), (gC, rC))]
+        _say("[c5] rel. Frobenius A, B, C:", errs)
+        assert max(errs) < tol, (prec, errs)
 
 
 def _synthetic_vectors(n_mock, P, seed):
