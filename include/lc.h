@@ -226,7 +226,7 @@ typedef struct {
  * lc_covariance: sample covariances over mocks and the linear construction.
  *   xi        DEVICE double [n_mock][3][P] from lc_xi_multipoles, P = n_r*n_mu + 3*n_r.
  *   n_mock    >= 2.
- *   m_a       random/data size ratio of R1 and R2 (1 in the paper, Sect. 4.4).
+ *   m_a       random/data size ratio of R1 and R2 (1 in the paper, Sect. 4.3).
  *   M         target ratio; INFINITY gives A (the infinite-random limit).
  *   A, B, C   DEVICE double [P][P] full symmetric, written; A and B may be NULL.
  *             C^a = (Cov x + Cov x')/2, C^b = Cov y, Cov = sum (v - mean)(v - mean)^T / (N - 1).
@@ -339,8 +339,10 @@ lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32_t P, int32
 /* Summary of lc_covcov (Sect. 5.3, Table 3). */
 typedef struct {
     double chi2_2_lc, chi2_2_smp;   /* <chi^2_2> of the LC and of the sample covariance */
-    double cost_lc, cost_smp;       /* pair-count cost per realisation (units of the pairs of
-                                       one data catalogue): 1 + 4 M_a + 2 M_a^2 and 1 + 3M */
+    double cost_lc, cost_smp;       /* pair-count cost per realisation in units of the pairs of
+                                       one data catalogue, N_d^2 / 2 (Sect. 2.3): LC counts DD
+                                       once and two split estimates with ratio M_a, 1 + 6 M_a;
+                                       the split sample covariance at ratio M, 1 + 3M */
     double ifom_lc, ifom_smp;       /* inverse figures of merit, cost x chi^2_2 */
     double gain;                    /* ifom_smp / ifom_lc */
 } lc_covcov_report;

@@ -278,9 +278,12 @@ def pair_cost_sample(M: float) -> float:
 
 
 def pair_cost_lc(m_a: int) -> float:
-    """Pair-count cost of one realisation for LC (Sect. 2.3): DD (1), DR1 and
-    DR2 (2 x 2 M_a), RR1 and RR2 (2 x M_a^2); 7 for M_a = 1."""
-    return 1.0 + 4.0 * m_a + 2.0 * m_a * m_a
+    """Pair-count cost of one realisation for LC (Sect. 2.3), in units of the
+    pairs of one data catalogue (N_d^2 / 2), with DD counted once: the two
+    split estimates with ratio M_a each cost DD (1) + DR (2 M_a) + M_a split
+    RR (M_a), and the shared DD is not counted again, so 1 + 6 M_a; 7 for
+    M_a = 1."""
+    return 1.0 + 6.0 * m_a
 
 
 def covcov_summary(A: np.ndarray, B: np.ndarray, m_a: int, M: float, Cref: Optional[np.ndarray] = None):

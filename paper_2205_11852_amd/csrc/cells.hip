@@ -1,7 +1,8 @@
 // Chaining mesh: counting sort of every catalogue into one shared grid of
 // cells, so that pair counting only visits cells that can hold pairs closer
 // than r_max.  Steps: (open geometry) bounding box -> cell id and per-cell
-// histogram -> exclusive scan -> scatter of float64 points.
+// histogram -> exclusive scan -> scatter of the points as float32 values
+// relative to their cell's integer origin.
 #include <algorithm>
 #include <cmath>
 

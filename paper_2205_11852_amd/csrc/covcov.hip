@@ -93,7 +93,9 @@ extern "C" lc_status lc_covcov(const double* A, const double* B, int32_t P, int3
         const double n2 = double(P) * double(P);
         rep->chi2_2_lc = lc_sum / n2;
         rep->chi2_2_smp = smp_sum / n2;
-        rep->cost_lc = 1.0 + 4.0 * m_a + 2.0 * double(m_a) * m_a;
+        // Sect. 2.3: two split estimates with ratio M_a, DD counted once:
+        // DD (1) + 2 x (DR 2 M_a + split RR M_a) in units of N_d^2 / 2
+        rep->cost_lc = 1.0 + 6.0 * double(m_a);
         rep->cost_smp = std::isinf(M) ? INFINITY : 1.0 + 3.0 * M;
         rep->ifom_lc = rep->cost_lc * rep->chi2_2_lc;
         rep->ifom_smp = rep->cost_smp * rep->chi2_2_smp;

@@ -527,11 +527,13 @@ def test_split_estimate_with_two_subsets_matches_xi_multipoles(c1, torch, lcmod)
     assert np.array_equal(a[np.isfinite(a)], b[np.isfinite(b)])
 
 
-@pytest.mark.parametrize("P,M,use_ref", [(37, 50.0, False), (2120, 50.0, False), (2120, 10.0, True),
-                                         (120, float("inf"), False)])
-def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref):
+@pytest.mark.parametrize("P,M,use_ref,m_a", [(37, 50.0, False, 1), (2120, 50.0, False, 1), (2120, 10.0, True, 1),
+                                             (120, float("inf"), False, 1), (37, 50.0, False, 2),
+                                             (300, 7.0, True, 2), (64, 9.0, False, 3)])
+def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref, m_a):
     """Covariance of the covariance estimates and the Table 3 summary on the
-    device against the oracle (float64, 1e-12)."""
+    device against the oracle (float64, 1e-12), for M_a = 1, 2 and 3 (the
+    pair-count cost 1 + 6 M_a of Sect. 2.3 included)."""
     r = np.random.default_rng(P)
     G1, G2 = r.normal(size=(P, P)) / np.sqrt(P), r.normal(size=(P, P)) / np.sqrt(P)
     A = G1 @ G1.T + 0.1 * np.eye(P)      # positive definite, like the covariances
@@ -542,16 +544,17 @@ def test_covcov_parity(torch, oracle_mod, lcmod, P, M, use_ref):
     sd_lc = torch.empty((P, P), dtype=torch.float64, device="cuda")
     sd_smp = torch.empty_like(sd_lc)
     n = 500
-    rep = lcmod.lc_covcov(dA, dB, P, 1, M, dref, n, sd_lc, sd_smp)
-    exp = oracle_mod.covcov_summary(A, B, 1, M, ref) if np.isfinite(M) else None
+    rep = lcmod.lc_covcov(dA, dB, P, m_a, M, dref, n, sd_lc, sd_smp)
+    exp = oracle_mod.covcov_summary(A, B, m_a, M, ref) if np.isfinite(M) else None
     if exp is not None:
         for k in ("chi2_2_lc", "chi2_2_smp", "ifom_lc", "ifom_smp", "gain"):
             assert abs(rep[k] - exp[k]) <= 1e-12 * abs(exp[k]), (k, rep[k], exp[k])
         assert rep["cost_lc"] == exp["cost_lc"] and rep["cost_smp"] == exp["cost_smp"]
     else:
-        exp_lc = oracle_mod.chi2_2(oracle_mod.lc_cov_element_var(A, B, 1, M, 2), A)
+        exp_lc = oracle_mod.chi2_2(oracle_mod.lc_cov_element_var(A, B, m_a, M, 2), A)
         assert abs(rep["chi2_2_lc"] - exp_lc) <= 1e-12 * exp_lc
-    v_lc = oracle_mod.lc_cov_element_var(A, B, 1, M, n)
+    assert rep["cost_lc"] == oracle_mod.pair_cost_lc(m_a)
+    v_lc = oracle_mod.lc_cov_element_var(A, B, m_a, M, n)
     v_smp = oracle_mod.sample_cov_element_var(A + (0.0 if np.isinf(M) else 1.0 / M) * B, n)
     assert np.allclose(sd_lc.cpu().numpy(), np.sqrt(v_lc), rtol=1e-12, atol=0)
     assert np.allclose(sd_smp.cpu().numpy(), np.sqrt(v_smp), rtol=1e-12, atol=0)

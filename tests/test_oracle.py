@@ -508,6 +508,91 @@ def test_table3_costs_and_figures_of_merit(oracle_mod):
         assert abs(i_smp / i_lc - ratio) <= _last_digit(row[8]) + 0.01 * ratio, row
 
 
+def _golden_value(txt):
+    from fractions import Fraction
+    if "/" in txt:
+        num, den = txt.split("/")
+        return float(Fraction(num) / Fraction(den))
+    return float(Fraction(txt))
+
+
+def _golden_matrix(txt, P):
+    if txt == "-":
+        return None
+    if txt == "0":
+        return np.zeros((P, P))
+    if txt.startswith("I*"):
+        return float(txt[2:]) * np.eye(P)
+    return np.array([[float(v) for v in row.split(",")] for row in txt.split(";")])
+
+
+def test_chi2_2_hand_derived_closed_forms(oracle_mod):
+    """<chi^2_2> of both estimators, the pair-count costs and the iFoMs
+    against values summed by hand (tests/golden/chi2_2_closed_forms.txt,
+    with the derivations; Sect. 2.3, 3.2, 3.3, 5.3).  The cases separate the
+    normalisation 1/P^2, the C_ii C_jj and C_ij^2 terms, D = A + B/(2 M_a),
+    the factor f^2 and the reference diagonal."""
+    for row in _golden("chi2_2_closed_forms.txt"):
+        name, P, m_a, M = row[0], int(row[1]), int(row[2]), float(row[3])
+        A, B = _golden_matrix(row[4], P), _golden_matrix(row[5], P)
+        ref = _golden_matrix(row[6], P)
+        x_smp, x_lc, c_smp, c_lc = (_golden_value(v) for v in row[7:11])
+        s = oracle_mod.covcov_summary(A, B, m_a, M, ref)
+        assert abs(s["chi2_2_smp"] - x_smp) <= 1e-12 * x_smp, (name, P, s["chi2_2_smp"], x_smp)
+        assert abs(s["chi2_2_lc"] - x_lc) <= 1e-12 * x_lc, (name, P, s["chi2_2_lc"], x_lc)
+        assert s["cost_smp"] == c_smp and s["cost_lc"] == c_lc, (name, s["cost_smp"], s["cost_lc"])
+        assert abs(s["ifom_lc"] - c_lc * x_lc) <= 1e-12 * c_lc * x_lc
+        assert abs(s["gain"] - (c_smp * x_smp) / (c_lc * x_lc)) <= 1e-12 * s["gain"]
+
+
+def test_lc_pair_cost_counts_dd_once(oracle_mod):
+    """Sect. 2.3: the split estimator at ratio M costs N_d^2/2 (1 + 3M); LC
+    runs it twice at ratio M_a, 2 x N_d^2/2 (1 + 3 M_a), and counting DD once
+    removes one N_d^2/2: 1 + 6 M_a.  The paper's M = 50, M_a = 1 gain
+    151/7."""
+    for m_a in (1, 2, 3, 5):
+        assert oracle_mod.pair_cost_lc(m_a) == 2 * oracle_mod.pair_cost_sample(m_a) - 1
+    assert oracle_mod.pair_cost_lc(1) == 7 and oracle_mod.pair_cost_lc(2) == 13
+    assert abs(oracle_mod.pair_cost_sample(50) / oracle_mod.pair_cost_lc(1) - 21.6) < 0.05
+
+
+def test_chi2_2_monte_carlo(oracle_mod):
+    """<chi^2_2> by simulation, with no use of the variance formulas: Gaussian
+    estimates x, x' with a known joint covariance, N = 2 realisations per
+    trial, 200000 trials.  The spread of every element of the sample
+    covariance and of the LC covariance (c^a = (c(x) + c(x'))/2, c^b from
+    (x + x')/2, M_a = 1) over the trials, divided by Cref_ii Cref_jj and
+    averaged over the P^2 elements, is the definition of Eq. chi2 at N = 2;
+    covcov_summary must agree within the Monte Carlo error."""
+    P, N, trials, m_a, M = 3, 2, 200000, 1, 10.0
+    S, T = _exchangeable(P, 17)
+    J = np.block([[S, T], [T, S]])
+    L = np.linalg.cholesky(J)
+    r = np.random.default_rng(18)
+    z = r.normal(size=(trials, N, 2 * P)) @ L.T
+    x, xp = z[..., :P], z[..., P:]
+
+    def scov(v):
+        d = v - v.mean(axis=1, keepdims=True)
+        return np.einsum("tni,tnj->tij", d, d) / (N - 1)
+
+    ca = 0.5 * (scov(x) + scov(xp))
+    cb = scov(0.5 * (x + xp))
+    C_lc = (2 * cb - ca) + 2 * m_a * (ca - cb) / M
+    A, B = T, m_a * (S - T)            # ensemble C^a = S, C^b = (S + T)/2
+    C_M = A + B / M                    # the covariance the LC estimates
+    # the sample covariance of an estimate with that covariance
+    Lm = np.linalg.cholesky(C_M)
+    w = r.normal(size=(trials, N, P)) @ Lm.T
+    C_smp = scov(w)
+    d = np.diag(C_M)
+    mc_lc = float((C_lc.var(axis=0, ddof=1) / np.outer(d, d)).mean())
+    mc_smp = float((C_smp.var(axis=0, ddof=1) / np.outer(d, d)).mean())
+    s = oracle_mod.covcov_summary(A, B, m_a, M)
+    assert abs(s["chi2_2_lc"] / mc_lc - 1.0) < 0.03, (s["chi2_2_lc"], mc_lc)
+    assert abs(s["chi2_2_smp"] / mc_smp - 1.0) < 0.03, (s["chi2_2_smp"], mc_smp)
+
+
 def test_covcov_summary_consistency(oracle_mod):
     """covcov_summary: chi^2_2 of the sample covariance equals the LC one when
     M = 2 M_a (the two estimators coincide there, Sect. 3.3), and the gain is
