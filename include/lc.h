@@ -161,6 +161,10 @@ typedef struct {
     int32_t chunk;            /* i points tested together against each gathered j set:
                                  a multiple of 4 in [4, 256];
                                  default the maximum */
+    int32_t flush_limit;      /* testing: candidate tests a wave may register before it moves
+                                 the block histogram out to counts (the overflow guard).
+                                 0 = the largest safe value, 2^32 / waves_per_block, which keeps
+                                 every uint32 bin from wrapping; a small value forces the guard */
 } lc_tuning;
 
 /*
@@ -173,9 +177,11 @@ typedef struct {
  *   mode     LC_PERSISTENT or LC_PER_TASK, optionally | LC_GRAPH | LC_FORCE_EXACT.
  *   tune     NULL for defaults.
  *   stats    DEVICE uint64 [4] or NULL, ADDED INTO: [0] candidate pair
- *            tests, [1] reserved (0), [2] pairs decided by the integer rule
- *            (their float estimate was within its error bound of an edge),
- *            [3] histogram flushes.  Binned pairs = the sum of counts.
+ *            tests, [1] overflow-guard flushes (a wave moved the block
+ *            histogram out before its task ended; see flush_limit), [2] pairs
+ *            decided by the integer rule (their float estimate was within its
+ *            error bound of an edge), [3] block flushes (task changes and the
+ *            end of each block's work).  Binned pairs = the sum of counts.
  * Asynchronous.  Counts are exact; the result does not depend on mode,
  * tuning, or the order in which tiles run.
  */
@@ -209,6 +215,9 @@ lc_status lc_xi_multipoles(const uint64_t* counts, const lc_task* tasks, int32_t
 #define LC_FP64               0  /* float64 covariance products */
 #define LC_FP32_MFMA          1  /* float32 MFMA products, float64 mean/combination/check */
 #define LC_FP32_MFMA_CHECKED  2  /* as LC_FP32_MFMA and also the float64 path, for the report */
+#define LC_ACC32              8  /* flag for the two float32 modes: accumulate the MFMA products in
+                                    float32 over all mocks; without it the float32 accumulators are
+                                    added into float64 every 256 mocks */
 
 /* Positive-definiteness report (Sect. 3: C^LC is not guaranteed to be
  * positive definite; check its spectrum).  Block 0 = the (r, mu) part
@@ -329,7 +338,7 @@ lc_status lc_map_matrix(const double* X, int32_t P_in, const int32_t* group, con
  *   x          DEVICE double [n_mock][P] (e.g. from lc_xi_split); n_mock >= 2.
  *   precision  LC_FP64, or LC_FP32_MFMA (float32 deviations, MFMA products
  *              accumulated in float32 over blocks of 256 mocks and summed in
- *              float64).
+ *              float64), optionally | LC_ACC32 (float32 over all mocks).
  *   C          DEVICE double [P][P], written (full symmetric).
  * Asynchronous; NaN entries propagate to their rows and columns.
  */

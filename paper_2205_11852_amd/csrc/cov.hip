@@ -10,8 +10,9 @@
 //   ->  Cholesky and eigenvalue extremes of each block of C (float64).
 //
 // The products D^T D run either in float64 (VALU) or as float32 MFMA
-// (v_mfma_f32_32x32x2f32) with float32 accumulation over chunks of 256
-// mocks whose partial sums are added in float64.
+// (v_mfma_f32_32x32x2f32) with float32 accumulation, by default over chunks
+// of 256 mocks whose partial sums are added in float64 (LC_ACC32: over all
+// mocks in float32).
 #include <algorithm>
 #include <cfloat>
 #include <cmath>
@@ -146,8 +147,10 @@ constexpr int kMT = 128;    // tile
 constexpr int kKT = 32;     // rows per LDS slab
 constexpr int kKC = 256;    // rows per float32 accumulation chunk
 
+// kc: rows summed in the float32 accumulators before they are added into
+// the float64 ones (a multiple of kKT; Npad or more: float32 throughout)
 __global__ __launch_bounds__(256) void k_syrk32(const float* __restrict__ dev, int64_t Npad, int64_t Ppad,
-                                                int64_t P, double denom, double* __restrict__ cov) {
+                                                int64_t P, int64_t kc, double denom, double* __restrict__ cov) {
     __shared__ __align__(16) float As[kKT][kMT];
     __shared__ __align__(16) float Bs[kKT][kMT];
     const int e = blockIdx.y;
@@ -191,7 +194,7 @@ __global__ __launch_bounds__(256) void k_syrk32(const float* __restrict__ dev, i
         }
         __syncthreads();
         since += kKT;
-        if (since == kKC || n0 + kKT >= Npad) {
+        if (since == kc || n0 + kKT >= Npad) {
             for (int a = 0; a < 2; a++)
                 for (int b = 0; b < 2; b++)
                     for (int r = 0; r < 16; r++) {
@@ -222,14 +225,17 @@ __global__ void k_combine(const double* __restrict__ cov, int64_t PP, double m_a
                           double* __restrict__ A, double* __restrict__ B, double* __restrict__ C) {
 #pragma clang fp contract(off)
     // Eq. CovAB: A = (M_b C^b - M_a C^a)/(M_b - M_a), B = M_a M_b/(M_b - M_a) (C^a - C^b);
-    // at M_b = 2 M_a these are 2 C^b - C^a and 2 M_a (C^a - C^b), bit for bit
+    // at M_b = 2 M_a (Eq. LCdef) the forms 2 C^b - C^a and 2 M_a (C^a - C^b)
+    // are used as written (the general quotient would round differently
+    // unless M_a is a power of two)
     const double dm = m_b - m_a;
-    const double kb = (m_a * m_b) / dm;
+    const bool paper = (m_b == 2.0 * m_a);
+    const double kb = paper ? 2.0 * m_a : (m_a * m_b) / dm;
     for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < PP;
          t += int64_t(gridDim.x) * blockDim.x) {
         const double ca = 0.5 * (cov[t] + cov[PP + t]);
         const double cb = cov[2 * PP + t];
-        const double a = (m_b * cb - m_a * ca) / dm;
+        const double a = paper ? 2.0 * cb - ca : (m_b * cb - m_a * ca) / dm;
         const double b = kb * (ca - cb);
         A[t] = a;
         B[t] = b;
@@ -708,9 +714,13 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
                                  double M, int32_t precision, double* A, double* B, double* C, lc_cov_report* rep,
                                  hipStream_t s) {
     if (!(M > 0.0)) return fail(LC_ERR_INVALID, "M must be > 0 (or INFINITY)");
+    const bool acc32 = (precision & LC_ACC32) != 0;
+    precision &= ~LC_ACC32;
     if (precision != LC_FP64 && precision != LC_FP32_MFMA && precision != LC_FP32_MFMA_CHECKED)
         return fail(LC_ERR_INVALID, "precision = %d is not LC_FP64 / LC_FP32_MFMA / LC_FP32_MFMA_CHECKED",
                     precision);
+    if (acc32 && precision == LC_FP64) return fail(LC_ERR_INVALID, "LC_ACC32 needs a float32 MFMA precision");
+    const int64_t kc = acc32 ? INT64_MAX : int64_t(kKC);
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
     (void)ctx;
@@ -751,7 +761,7 @@ static lc_status covariance_impl(const double* xi, int32_t n_mock, int64_t P, in
         LC_TRY(dev.alloc(size_t(3 * Npad * Ppad), s));
         k_dev32<<<nblocks(3 * Npad * Ppad, 256, 65536), 256, 0, s>>>(xi, mean, N, P, 3, Npad, Ppad, dev.get());
         const int64_t T = Ppad / kMT;
-        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev.get(), Npad, Ppad, P, denom, covbuf);
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 3), 256, 0, s>>>(dev.get(), Npad, Ppad, P, kc, denom, covbuf);
         return LC_OK;
     };
     if (precision == LC_FP64) {
@@ -845,8 +855,12 @@ extern "C" lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32
     if (!x || !C) return fail(LC_ERR_INVALID, "x and C must not be NULL");
     if (n_mock < 2) return fail(LC_ERR_INVALID, "n_mock = %d, need >= 2", n_mock);
     if (P < 1 || P > 4 * LC_MAX_BINS) return fail(LC_ERR_INVALID, "P = %d out of range", P);
+    const bool acc32 = (precision & LC_ACC32) != 0;
+    precision &= ~LC_ACC32;
     if (precision != LC_FP64 && precision != LC_FP32_MFMA)
         return fail(LC_ERR_INVALID, "precision = %d is not LC_FP64 / LC_FP32_MFMA", precision);
+    if (acc32 && precision == LC_FP64) return fail(LC_ERR_INVALID, "LC_ACC32 needs LC_FP32_MFMA");
+    const int64_t kc = acc32 ? INT64_MAX : int64_t(kKC);
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
     (void)ctx;
@@ -877,7 +891,7 @@ extern "C" lc_status lc_sample_covariance(const double* x, int32_t n_mock, int32
         LC_TRY(dev.alloc(size_t(Npad * Ppad), s));
         k_dev32<<<nblocks(Npad * Ppad, 256, 65536), 256, 0, s>>>(x, mean, N, PL, 1, Npad, Ppad, dev.get());
         const int64_t T = Ppad / kMT;
-        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 1), 256, 0, s>>>(dev.get(), Npad, Ppad, PL, denom, C);
+        k_syrk32<<<dim3(unsigned(T * (T + 1) / 2), 1), 256, 0, s>>>(dev.get(), Npad, Ppad, PL, kc, denom, C);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(LC_ERR_HIP, "covariance launch failed: %s", hipGetErrorString(e));

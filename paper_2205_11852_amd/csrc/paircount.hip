@@ -229,7 +229,8 @@ struct WaveState {
     uint32_t since_flush; // candidate tests this wave registered since its last flush
     uint64_t n_cand;
     uint32_t n_exact;     // per lane: pairs binned by the integer rule
-    uint32_t n_flush;
+    uint32_t n_flush;     // block flushes (task changes), counted by thread 0
+    uint32_t n_wflush;    // this wave's overflow-guard flushes
 };
 
 extern __shared__ __align__(16) unsigned char smem[];
@@ -424,7 +425,7 @@ __device__ __forceinline__ void wave_flush(WaveState& w, int lane, const PcParam
         if (v) __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     w.since_flush = 0;
-    w.n_flush++;
+    w.n_wflush++;
 }
 
 // End of a task: every wave has binned its queue; the block adds the
@@ -584,7 +585,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     w.qtail = 0;
     w.since_flush = 0;
     w.n_cand = 0;
-    w.n_exact = w.n_flush = 0;
+    w.n_exact = w.n_flush = w.n_wflush = 0;
     for (int b = threadIdx.x; b < p.hist_stride; b += blockDim.x) w.hist[b] = 0;
 
     // work items are taken by the whole block (thread 0 pops, the others read
@@ -709,8 +710,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     const float jw = LOS == 1 ? __int_as_float(int(uint32_t(jb_pend.idx - w.b0) * 12u)) : 0.0f;
                     const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
                     w.n_cand += nc;
-                    // keep this wave's share of the bound on every bin (nc <= 2^14)
-                    if (w.since_flush + uint32_t(nc) >= p.wave_limit)
+                    // keep this wave's share of the bound on every bin (nc <= 2^14;
+                    // the sum is taken in 64 bits, so a limit of 2^32 - 1 cannot wrap)
+                    if (uint64_t(w.since_flush) + nc >= uint64_t(p.wave_limit))
                         wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
                     w.since_flush += uint32_t(nc);
                     if (__builtin_amdgcn_ballot_w64(vj && jb_pend.self))
@@ -811,7 +813,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
         if (w.n_exact) atomicAdd(&stats[2], (unsigned long long)w.n_exact);
         if (lane == 0) {
             atomicAdd(&stats[0], (unsigned long long)w.n_cand);
-            atomicAdd(&stats[3], (unsigned long long)w.n_flush);
+            if (w.n_wflush) atomicAdd(&stats[1], (unsigned long long)w.n_wflush);
+            if (w.n_flush) atomicAdd(&stats[3], (unsigned long long)w.n_flush);
         }
     }
 }
@@ -1031,8 +1034,10 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     }
     pl.threads = wpb * 64;
     pl.lds = lds_for(wpb);
-    // each wave's share of the 2^32 bound on a histogram bin
+    // each wave's share of the 2^32 bound on a histogram bin; a smaller
+    // flush_limit (testing) makes waves take the overflow guard early
     p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
+    if (tune && tune->flush_limit > 0) p.wave_limit = std::min(p.wave_limit, uint32_t(tune->flush_limit));
     occ = std::max(occ, 1);
     int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, occ) : occ;
     pl.blocks = ctx->n_cu * bpc;
@@ -1226,14 +1231,9 @@ void forget_graphs(const lc_cells* cells) {
     }
 }
 
-}  // namespace lc
-
-using namespace lc;
-
-extern "C" lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
-                                         const lc_binning* b, uint64_t* counts, int32_t mode,
-                                         const lc_tuning* tune, uint64_t* stats, void* stream) {
-    clear_error();
+// Argument checks shared by the two pair-count entry points.
+static lc_status check_count_args(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
+                                  const lc_binning* b, uint64_t* counts, int32_t mode) {
     if (!cells) return fail(LC_ERR_INVALID, "cells is NULL");
     LC_TRY(check_binning(b));
     if (n_tasks < 0) return fail(LC_ERR_INVALID, "n_tasks < 0");
@@ -1252,6 +1252,19 @@ extern "C" lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* t
             tasks[t].cat_b >= cells->n_cat)
             return fail(LC_ERR_INVALID, "task %d has catalogue ids (%d, %d) outside [0, %d)", t,
                         tasks[t].cat_a, tasks[t].cat_b, cells->n_cat);
+    return LC_OK;
+}
+
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
+                                         const lc_binning* b, uint64_t* counts, int32_t mode,
+                                         const lc_tuning* tune, uint64_t* stats, void* stream) {
+    clear_error();
+    LC_TRY(check_count_args(cells, tasks, n_tasks, b, counts, mode));
+    if (n_tasks == 0) return LC_OK;
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));
     if (ctx->device != cells->device) return fail(LC_ERR_INVALID, "mesh lives on another device");

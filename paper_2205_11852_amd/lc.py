@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblc.so")
 LC_OK, LC_ERR_INVALID, LC_ERR_RANGE, LC_ERR_OVERFLOW, LC_ERR_HIP, LC_ERR_NOMEM = 0, -1, -2, -3, -4, -5
 LC_LOS_Z, LC_LOS_MID, LC_LOS_RPPI = 0, 1, 2
 LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
-LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED = 0, 1, 2
+LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED, LC_ACC32 = 0, 1, 2, 8
 LC_MAX_BINS, LC_MAX_NMU = 32768, 1024
 
 STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ERR_OVERFLOW",
@@ -56,7 +56,8 @@ class lc_task(ctypes.Structure):
 
 class lc_tuning(ctypes.Structure):
     _fields_ = [("cells_per_item", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("flush_limit", ctypes.c_int32)]
 
 
 class lc_mesh_opts(ctypes.Structure):
@@ -281,7 +282,8 @@ def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int
     tn = None
     if tune:
         tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
-                       int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)))
+                       int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)),
+                       int(tune.get("flush_limit", 0)))
     _check(lib().lc_pair_count_batch(cells.handle if cells else None, t.ctypes.data, len(t),
                                      ctypes.byref(binning.c), _dptr(counts), int(mode),
                                      ctypes.byref(tn) if tn is not None else None, _dptr(stats),

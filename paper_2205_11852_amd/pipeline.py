@@ -323,4 +323,4 @@ class Pipeline:
     def stats_host(self) -> Dict[str, int]:
         s = self.stats.cpu().numpy().view(np.uint64)
         return {"candidates": int(s[0]), "binned": int(self.counts_host().sum(dtype=np.uint64)),
-                "exact_fallback": int(s[2]), "flushes": int(s[3])}
+                "exact_fallback": int(s[2]), "flushes": int(s[3]), "guard_flushes": int(s[1])}

@@ -134,7 +134,9 @@ def test_xi_rejects_inconsistent_tasks(L):
     (dict(m_a=0), lc.LC_ERR_INVALID),
     (dict(M=0.0), lc.LC_ERR_INVALID),
     (dict(M=float("nan")), lc.LC_ERR_INVALID),
-    (dict(precision=9), lc.LC_ERR_INVALID),
+    (dict(precision=3), lc.LC_ERR_INVALID),
+    (dict(precision=lc.LC_FP64 | lc.LC_ACC32), lc.LC_ERR_INVALID),    # float32 accumulation needs MFMA
+    (dict(precision=16 | lc.LC_FP32_MFMA), lc.LC_ERR_INVALID),
     (dict(n_mu=0), lc.LC_ERR_INVALID),
     (dict(C=0), lc.LC_ERR_INVALID),
 ])
@@ -209,7 +211,8 @@ def test_covariance_general_rejects_bad_arguments(L):
     assert call(ma=0.0) == lc.LC_ERR_INVALID
     assert call(mb=float("inf")) == lc.LC_ERR_INVALID
     assert call(M=0.0) == lc.LC_ERR_INVALID
-    assert call(prec=9) == lc.LC_ERR_INVALID
+    assert call(prec=3) == lc.LC_ERR_INVALID
+    assert call(prec=lc.LC_FP64 | lc.LC_ACC32) == lc.LC_ERR_INVALID
 
 
 def test_rebin_counts_rejects_bad_arguments(L):

@@ -214,11 +214,13 @@ def test_c5_sampled_tasks_and_data_vector(c5, oracle_mod):
 def test_c5_covariance_precision_against_oracle(c5, oracle_mod, lcmod, torch):
     """The 5000 measured data vectors (P = 2120): the float32-MFMA products
     give A, B and C^LC(50) within 1e-5 (relative Frobenius) of the float64
-    oracle's, and the float64 path within 1e-12."""
+    oracle's, with float32 accumulation over blocks of 256 mocks and over all
+    5000 (LC_ACC32), and the float64 path within 1e-12."""
     pl = c5["pl"]
     V = c5["xi"]
     rA, rB, rC, _, _ = oracle_mod.lc_from_vectors(V, 1, 50.0)
-    for prec, tol in ((lcmod.LC_FP32_MFMA, 1e-5), (lcmod.LC_FP64, 1e-12)):
+    for prec, tol in ((lcmod.LC_FP32_MFMA, 1e-5), (lcmod.LC_FP32_MFMA | lcmod.LC_ACC32, 1e-5),
+                      (lcmod.LC_FP64, 1e-12)):
         _say("[c5] covariance, precision", prec)
         pl.covariance(prec, report=False, M=50.0)
         torch.cuda.synchronize()
@@ -246,7 +248,8 @@ def test_covariance_full_size(lcmod, oracle_mod, torch, n_mock):
     xi = torch.from_numpy(V).cuda()
     A, B, C = (torch.empty((P, P), dtype=torch.float64, device="cuda") for _ in range(3))
     rA, rB, rC, _, _ = oracle_mod.lc_from_vectors(V, 1, 50.0)
-    for prec, tol in ((lcmod.LC_FP32_MFMA_CHECKED, 1e-5), (lcmod.LC_FP64, 1e-12)):
+    for prec, tol in ((lcmod.LC_FP32_MFMA_CHECKED | lcmod.LC_ACC32, 1e-5), (lcmod.LC_FP32_MFMA_CHECKED, 1e-5),
+                      (lcmod.LC_FP64, 1e-12)):
         _say("[cov] n_mock", n_mock, "precision", prec)
         rep = lcmod.lc_covariance(xi, n_mock, n_r, n_mu, 1, 50.0, prec, A, B, C, report=True)
         torch.cuda.synchronize()

@@ -451,6 +451,63 @@ def test_maximum_bins_bit_exact(torch, lcmod, oracle_mod):
         lcmod.lc_build_cells(xyz, cats.offsets, lcmod.Binning(edges + [edges[-1] + 1], 1024, True, L))
 
 
+@pytest.mark.parametrize("case", ["c1", "wedge", "max_bins"])
+def test_overflow_guard_bit_exact(torch, lcmod, oracle_mod, case):
+    """The overflow guard (a wave that has registered its share of the 2^32
+    bound on a uint32 bin moves the live block histogram out with atomic
+    exchanges while the block's other waves keep adding to it), forced by a
+    small flush_limit, with 4- and 16-wave blocks and per-task launches:
+    counts bit-exact against the oracle, and the guard taken many times
+    (stats[1], apart from the block flushes in stats[3])."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    if case == "c1":
+        cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"], 6)
+        wl = cats.wl
+        edges, n_mu, box, los = wl.r_edges_units, wl.n_mu, wl.box_units, "z"
+        bn = None
+    elif case == "wedge":
+        wl = dataclasses.replace(mockgen.WORKLOADS["c4"], n_mock=2, n_mean=6000.0, n_parents=300,
+                                 n_subsets=2, subset_size=6000)
+        cats = mockgen.make_catalogues(wl)
+        edges, n_mu, box, los = wl.r_edges_units, wl.n_mu, 0, "mid"
+        bn = None
+    else:
+        cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"], 2)
+        box = cats.wl.box_units
+        edges = list(range(0, 33 * 3 * mockgen.UNITS_PER_MPC, 3 * mockgen.UNITS_PER_MPC))
+        n_mu, los = 1024, "z"
+        bn = lcmod.Binning(edges, n_mu, True, box, lcmod.LC_LOS_Z)
+    pl = Pipeline(cats)
+    if bn is not None:
+        pl.binning = bn
+        pl.counts = torch.zeros((len(pl.tasks), bn.n_r, n_mu), dtype=torch.int64, device="cuda")
+    pl.build_cells()
+    refs = [oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), edges, n_mu, box, los)
+            for a, b in pl.tasks]
+    runs = [(lcmod.LC_PERSISTENT, dict(flush_limit=3000)),
+            (lcmod.LC_PERSISTENT, dict(flush_limit=20000, waves_per_block=16)),
+            (lcmod.LC_PER_TASK, dict(flush_limit=5000))]
+    if case != "max_bins":
+        # a flush after every gathered j block (the 32768-bin histogram would
+        # make this slow)
+        runs.append((lcmod.LC_PERSISTENT, dict(flush_limit=1, waves_per_block=4, chunk=64)))
+    for mode, tune in runs:
+        _say("[guard]", case, "mode", mode, "tune", tune)
+        pl.count(mode, tune)
+        torch.cuda.synchronize()
+        gpu = pl.counts_host()
+        for t in range(len(pl.tasks)):
+            assert np.array_equal(gpu[t], refs[t]), (case, mode, tune, t)
+        st = pl.stats_host()
+        _say("[guard]", case, st)
+        assert st["guard_flushes"] > 100, st
+        assert st["flushes"] > 0
+    # the default limit never takes the guard on these workloads
+    pl.count()
+    torch.cuda.synchronize()
+    assert pl.stats_host()["guard_flushes"] == 0
+
+
 def test_out_of_box_coordinate_is_an_error(torch, lcmod):
     L = 1000
     xyz = torch.tensor([[1, 2, L], [3, 4, 5], [6, 7, 8]], dtype=torch.int32, device="cuda")
