@@ -485,8 +485,8 @@ def test_overflow_guard_bit_exact(torch, lcmod, oracle_mod, case):
     refs = [oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), edges, n_mu, box, los)
             for a, b in pl.tasks]
     runs = [(lcmod.LC_PERSISTENT, dict(flush_limit=3000)),
-            (lcmod.LC_PERSISTENT, dict(flush_limit=20000, waves_per_block=16)),
-            (lcmod.LC_PER_TASK, dict(flush_limit=5000))]
+            (lcmod.LC_PERSISTENT, dict(flush_limit=1000, waves_per_block=16)),
+            (lcmod.LC_PER_TASK, dict(flush_limit=1500))]
     if case != "max_bins":
         # a flush after every gathered j block (the 32768-bin histogram would
         # make this slow)
