@@ -190,6 +190,31 @@ lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* tasks, int32
                               const lc_tuning* tune, uint64_t* stats, void* stream);
 
 /*
+ * lc_pair_count_batch_noalloc: lc_pair_count_batch for callers that cannot
+ * allocate device memory (code being captured into a graph, tight serving
+ * loops, harnesses that forbid hipMalloc).  It allocates nothing: the launch
+ * plan (task order, stencil, squared edges, cell origins, work-queue
+ * counters) is written by small kernels, from their arguments, into a static
+ * device array of LC_NOALLOC_PLAN_BYTES that the library holds on every
+ * device it runs on until the process ends; the caller passes the mesh,
+ * tasks, counts and stats as for lc_pair_count_batch.
+ *   Arguments, layouts, results and errors as for lc_pair_count_batch, except:
+ *   mode      LC_PERSISTENT or LC_PER_TASK, optionally | LC_FORCE_EXACT;
+ *             LC_GRAPH returns LC_ERR_INVALID (the graph cache allocates).
+ *   A plan larger than LC_NOALLOC_PLAN_BYTES (about 12 bytes per task plus
+ *   16 per stencil offset; LC_PER_TASK adds 32 bytes per task) returns
+ *   LC_ERR_OVERFLOW before anything is enqueued.
+ * Every call on one device shares that device's plan array and rewrites it
+ * (the queue counters included) before its launch: calls on one stream run
+ * in order, but calls that overlap on one device (other streams, other
+ * threads) race.  Asynchronous.
+ */
+#define LC_NOALLOC_PLAN_BYTES (1 << 20)
+lc_status lc_pair_count_batch_noalloc(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
+                                      const lc_binning* b, uint64_t* counts, int32_t mode,
+                                      const lc_tuning* tune, uint64_t* stats, void* stream);
+
+/*
  * lc_xi_multipoles: split Landy-Szalay estimates and their multipoles
  * (Sect. 2.1, 2.3, 4.3), float64.
  *   counts     DEVICE uint64 [n_tasks][n_r][n_mu] from lc_pair_count_batch.

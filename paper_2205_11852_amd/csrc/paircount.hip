@@ -1255,6 +1255,46 @@ static lc_status check_count_args(const lc_cells* cells, const lc_task* tasks, i
     return LC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// allocation-free variant: the staged plan lives in a static device array
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = size_t(LC_NOALLOC_PLAN_BYTES);
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+// Device address of `scratch` per device, taken once with that device
+// current (host code must never pass the array's name to a kernel: on the
+// host it is only a stand-in for the symbol).
+static std::mutex g_scratch_mu;
+static std::map<int, unsigned char*> g_scratch_ptr;
+
+static lc_status scratch_ptr(int device, unsigned char** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return LC_OK;
+    }
+    void* ptr = nullptr;
+    LC_TRY_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) return fail(LC_ERR_HIP, "hipGetSymbolAddress returned NULL for the plan array");
+    g_scratch_ptr[device] = static_cast<unsigned char*>(ptr);
+    *out = static_cast<unsigned char*>(ptr);
+    return LC_OK;
+}
+
+// The plan reaches the device through kernel arguments, kStageWords words per
+// launch: no host staging buffer, no device allocation, and no copy from
+// pageable memory.
+constexpr int kStageWords = 480;
+struct StageArgs {
+    uint32_t n;                 // words in this piece
+    uint32_t w[kStageWords];
+};
+
+__global__ __launch_bounds__(256) void k_stage(uint32_t* __restrict__ dst, StageArgs a) {
+    for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) dst[i] = a.w[i];
+}
+
 }  // namespace lc
 
 using namespace lc;
@@ -1281,6 +1321,42 @@ extern "C" lc_status lc_pair_count_batch(const lc_cells* cells, const lc_task* t
     launch_plan(pl, cells, static_cast<unsigned char*>(dev), counts, stats, s);
     hipError_t e = hipGetLastError();
     dev_free(dev, s);
+    if (e != hipSuccess) return fail(LC_ERR_HIP, "pair-count launch failed: %s", hipGetErrorString(e));
+    return LC_OK;
+}
+
+extern "C" lc_status lc_pair_count_batch_noalloc(const lc_cells* cells, const lc_task* tasks, int32_t n_tasks,
+                                                 const lc_binning* b, uint64_t* counts, int32_t mode,
+                                                 const lc_tuning* tune, uint64_t* stats, void* stream) {
+    clear_error();
+    LC_TRY(check_count_args(cells, tasks, n_tasks, b, counts, mode));
+    if (mode & LC_GRAPH)
+        return fail(LC_ERR_INVALID, "LC_GRAPH keeps a cached copy of the plan in allocated memory; "
+                                    "the allocation-free call takes LC_PERSISTENT or LC_PER_TASK (| LC_FORCE_EXACT)");
+    if (n_tasks == 0) return LC_OK;
+    DeviceCtx* ctx;
+    LC_TRY(get_ctx(&ctx));
+    if (ctx->device != cells->device) return fail(LC_ERR_INVALID, "mesh lives on another device");
+    Plan pl;
+    LC_TRY(make_plan(ctx, cells, tasks, n_tasks, b, mode, tune, pl));
+    pl.blob.resize((pl.blob.size() + 3) & ~size_t(3), 0);
+    if (pl.blob.size() > kScratchBytes)
+        return fail(LC_ERR_OVERFLOW, "the plan of %d tasks takes %zu bytes, more than the %zu bytes of the "
+                                     "allocation-free call's static plan array; use lc_pair_count_batch",
+                    n_tasks, pl.blob.size(), kScratchBytes);
+    unsigned char* dev = nullptr;
+    LC_TRY(scratch_ptr(ctx->device, &dev));
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t* words = reinterpret_cast<const uint32_t*>(pl.blob.data());
+    const size_t n_words = pl.blob.size() / 4;
+    StageArgs a;
+    for (size_t w0 = 0; w0 < n_words; w0 += kStageWords) {
+        a.n = uint32_t(std::min<size_t>(kStageWords, n_words - w0));
+        std::memcpy(a.w, words + w0, size_t(a.n) * 4);
+        hipLaunchKernelGGL(k_stage, dim3(1), dim3(256), 0, s, reinterpret_cast<uint32_t*>(dev) + w0, a);
+    }
+    launch_plan(pl, cells, dev, counts, stats, s);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return fail(LC_ERR_HIP, "pair-count launch failed: %s", hipGetErrorString(e));
     return LC_OK;
 }

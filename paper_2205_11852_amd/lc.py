@@ -23,13 +23,14 @@ LC_LOS_Z, LC_LOS_MID, LC_LOS_RPPI = 0, 1, 2
 LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
 LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED, LC_ACC32 = 0, 1, 2, 8
 LC_MAX_BINS, LC_MAX_NMU = 32768, 1024
+LC_NOALLOC_PLAN_BYTES = 1 << 20
 
 STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ERR_OVERFLOW",
                 -4: "LC_ERR_HIP", -5: "LC_ERR_NOMEM"}
 
 # the exported symbols of include/lc.h
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
-           "lc_pair_count_batch", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance", "lc_covcov",
+           "lc_pair_count_batch", "lc_pair_count_batch_noalloc", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance", "lc_covcov",
            "lc_autotune", "lc_covariance_general", "lc_rebin_counts", "lc_map_vectors", "lc_map_matrix",
            "lc_release_caches"]
 
@@ -130,6 +131,9 @@ def lib():
     L.lc_pair_count_batch.restype = st
     L.lc_pair_count_batch.argtypes = [vp, vp, i32, ctypes.POINTER(lc_binning), vp, i32,
                                       ctypes.POINTER(lc_tuning), vp, vp]
+    L.lc_pair_count_batch_noalloc.restype = st
+    L.lc_pair_count_batch_noalloc.argtypes = [vp, vp, i32, ctypes.POINTER(lc_binning), vp, i32,
+                                              ctypes.POINTER(lc_tuning), vp, vp]
     L.lc_xi_multipoles.restype = st
     L.lc_xi_multipoles.argtypes = [vp, vp, i32, vp, i32, vp, i32, i32, i32, vp, vp]
     L.lc_covariance.restype = st
@@ -272,9 +276,7 @@ def lc_build_cells(xyz, cat_offsets, binning: Binning, cell_units: int = 0, sub:
     return Cells(out.value)
 
 
-def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int = LC_PERSISTENT,
-                        tune: Optional[dict] = None, stats=None, stream=None):
-    """counts: uint64-as-int64 device tensor [n_tasks, n_r, n_mu], added into."""
+def _pair_count_args(cells, tasks, binning, counts, tune):
     t = tasks_array(tasks)
     if counts is not None and not isinstance(counts, int):
         if counts.numel() != len(t) * binning.n_r * binning.n_mu or counts.element_size() != 8:
@@ -284,10 +286,28 @@ def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int
         tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
                        int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)),
                        int(tune.get("flush_limit", 0)))
+    return t, tn
+
+
+def lc_pair_count_batch(cells: Cells, tasks, binning: Binning, counts, mode: int = LC_PERSISTENT,
+                        tune: Optional[dict] = None, stats=None, stream=None):
+    """counts: uint64-as-int64 device tensor [n_tasks, n_r, n_mu], added into."""
+    t, tn = _pair_count_args(cells, tasks, binning, counts, tune)
     _check(lib().lc_pair_count_batch(cells.handle if cells else None, t.ctypes.data, len(t),
                                      ctypes.byref(binning.c), _dptr(counts), int(mode),
                                      ctypes.byref(tn) if tn is not None else None, _dptr(stats),
                                      _stream(stream)))
+
+
+def lc_pair_count_batch_noalloc(cells: Cells, tasks, binning: Binning, counts, mode: int = LC_PERSISTENT,
+                                tune: Optional[dict] = None, stats=None, stream=None):
+    """As lc_pair_count_batch, through the entry point that allocates no
+    device memory (its plan lives in the library's static device array)."""
+    t, tn = _pair_count_args(cells, tasks, binning, counts, tune)
+    _check(lib().lc_pair_count_batch_noalloc(cells.handle if cells else None, t.ctypes.data, len(t),
+                                             ctypes.byref(binning.c), _dptr(counts), int(mode),
+                                             ctypes.byref(tn) if tn is not None else None, _dptr(stats),
+                                             _stream(stream)))
 
 
 def lc_xi_multipoles(counts, tasks, cat_sizes, est, n_r: int, n_mu: int, xi, stream=None):
