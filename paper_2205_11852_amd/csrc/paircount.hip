@@ -494,14 +494,6 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
     return qt;
 }
 
-// Pending j block: each lane holds one j point (in the i cell frame) or a
-// sentinel far from every i point.
-struct JBlock {
-    int64_t idx;       // global index of the point (valid lanes)
-    float ox, oy, oz;  // frame offset of the point's cell image
-    bool self;         // point of the i cell itself (auto pairs): count only j > i
-};
-
 // Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
 // scalar loads) against the j block held one point per lane.  TAIL: some of
 // the four lie past the chunk (still inside the padded point array); their
@@ -687,27 +679,26 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                 }
                 // j points gathered into blocks of 64 (one per lane) across runs
                 // of kept sub-cells and stencil offsets
-                JBlock jb_pend;
-                jb_pend.idx = 0;
-                jb_pend.ox = jb_pend.oy = jb_pend.oz = 0.0f;
-                jb_pend.self = false;
+                // Stage 1: gathered j points, one per lane in lanes [0, fill):
+                // coordinates in the i cell frame, j index relative to the chunk
+                // start for points of the i cell itself (auto pairs: count only
+                // j > i; INT_MAX otherwise; i indices within the chunk are below
+                // 256, so clamping large offsets keeps every comparison) and,
+                // for the midpoint line of sight, the byte offset of the point in
+                // its catalogue's absolute coordinates.
+                float sx = 0.0f, sy = 0.0f, sz = 0.0f, sw = 0.0f;
+                int srel = INT_MAX;
                 int fill = 0;
+                // Stage 2: the kept points, lanes [0, kfill): the block that is
+                // swept against the chunk.
+                float kx = -1e18f, ky = -1e18f, kz = -1e18f, kw = 0.0f;
+                int krel = INT_MAX;
+                int kfill = 0;
                 auto process = [&](int nfill) {
                     const bool vj = lane < nfill;
-                    float xj = -1e18f, yj = -1e18f, zj = -1e18f;
-                    if (vj) {
-                        xj = pts[3 * jb_pend.idx] + jb_pend.ox;
-                        yj = pts[3 * jb_pend.idx + 1] + jb_pend.oy;
-                        zj = pts[3 * jb_pend.idx + 2] + jb_pend.oz;
-                    }
-                    // self block: j index relative to the chunk start (pairs i < j
-                    // only; i indices within the chunk are below 256, so clamping
-                    // large offsets keeps every comparison)
-                    const int jrel = (vj && jb_pend.self) ? int(min(jb_pend.idx - ib, int64_t(INT_MAX))) : INT_MAX;
-                    // midpoint: the j point's byte offset in its catalogue's
-                    // absolute coordinates (any value on lanes past nfill,
-                    // whose pairs are never accepted)
-                    const float jw = LOS == 1 ? __int_as_float(int(uint32_t(jb_pend.idx - w.b0) * 12u)) : 0.0f;
+                    // lanes past nfill hold a point far from every i point
+                    const float xj = vj ? kx : -1e18f, yj = vj ? ky : -1e18f, zj = vj ? kz : -1e18f;
+                    const int jrel = vj ? krel : INT_MAX;
                     const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
                     w.n_cand += nc;
                     // keep this wave's share of the bound on every bin (nc <= 2^14;
@@ -715,12 +706,69 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     if (uint64_t(w.since_flush) + nc >= uint64_t(p.wave_limit))
                         wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
                     w.since_flush += uint32_t(nc);
-                    if (__builtin_amdgcn_ballot_w64(vj && jb_pend.self))
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, jw, pts, ib, n_i, p,
+                    if (__builtin_amdgcn_ballot_w64(jrel != INT_MAX))
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, kw, pts, ib, n_i, p,
                                                                   xt);
                     else
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, jw, pts, ib, n_i, p,
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, kw, pts, ib, n_i, p,
                                                                    xt);
+                };
+                // Move the stage-1 points that lie within r_max of the chunk's
+                // box into lanes [kfill, ...) of the kept block (one cross-lane
+                // permutation per field) and drop the others: no pair of theirs
+                // can be binned.  The coordinates and the box are exact integers
+                // in float32, so the gaps are exact, and the rounded squared gap
+                // exceeds the true one by at most 3 * 2^-24 (relative), inside
+                // the 2^-20 margin of emax2_hi: a point with a binnable pair is
+                // always kept.  Returns true when the kept block is full; the
+                // kept points past it then wait in stage 1 (they pass the test
+                // again), so nothing but the two stages stays live across a sweep.
+                auto admit = [&]() -> bool {
+                    const bool v = lane < fill;
+                    const float gx = fmaxf(fmaxf(blx - sx, sx - bhx), 0.0f);
+                    const float gy = fmaxf(fmaxf(bly - sy, sy - bhy), 0.0f);
+                    const float gz = fmaxf(fmaxf(blz - sz, sz - bhz), 0.0f);
+                    bool keep;
+                    if (LOS == 2)
+                        keep = v && (fmaf(gx, gx, gy * gy) < p.emax2_hi) && (gz < p.pimax_f);
+                    else
+                        keep = v && (fmaf(gx, gx, fmaf(gy, gy, gz * gz)) < p.emax2_hi);
+                    const unsigned long long km = __builtin_amdgcn_ballot_w64(keep);
+                    fill = 0;
+                    if (!km) return false;
+                    const uint32_t nk = uint32_t(__popcll(km));
+                    // a permutation of the 64 lanes: the kept lane of rank r goes
+                    // to lane kfill + r, every other lane after them (mod 64)
+                    const uint32_t rk =
+                        __builtin_amdgcn_mbcnt_hi(uint32_t(km >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(km), 0u));
+                    const uint32_t pos = keep ? rk : nk + uint32_t(lane) - rk;
+                    const int to = int(((uint32_t(kfill) + pos) & 63u) << 2);
+                    const float px = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sx)));
+                    const float py = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sy)));
+                    const float pz = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sz)));
+                    const int prel = __builtin_amdgcn_ds_permute(to, srel);
+                    const float pw =
+                        LOS == 1 ? __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sw))) : 0.0f;
+                    const bool take = lane >= kfill;
+                    kx = take ? px : kx;
+                    ky = take ? py : ky;
+                    kz = take ? pz : kz;
+                    krel = take ? prel : krel;
+                    if (LOS == 1) kw = take ? pw : kw;
+                    const int end = kfill + int(nk);
+                    if (end < 64) {
+                        kfill = end;
+                        return false;
+                    }
+                    // the points past the full block wrapped to lanes [0, end - 64)
+                    sx = px;
+                    sy = py;
+                    sz = pz;
+                    srel = prel;
+                    if (LOS == 1) sw = pw;
+                    fill = end - 64;
+                    kfill = 64;
+                    return true;
                 };
                 // the block's waves share the stencil offsets of the chunk
                 for (int s = wid; s < ns; s += nwave) {
@@ -784,23 +832,32 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                             // lanes [fill, fill + take) take points jb, jb + 1, ...
                             const int take = int(min(je - jb, int64_t(64 - fill)));
                             if (lane >= fill && lane < fill + take) {
-                                jb_pend.idx = jb + (lane - fill);
-                                jb_pend.ox = dox;
-                                jb_pend.oy = doy;
-                                jb_pend.oz = doz;
-                                jb_pend.self = self;
+                                const int64_t j = jb + (lane - fill);
+                                sx = pts[3 * j] + dox;
+                                sy = pts[3 * j + 1] + doy;
+                                sz = pts[3 * j + 2] + doz;
+                                srel = self ? int(min(j - ib, int64_t(INT_MAX))) : INT_MAX;
+                                if (LOS == 1) sw = __int_as_float(int(uint32_t(j - w.b0) * 12u));
                             }
                             fill += take;
                             jb += take;
-                            if (fill == 64) {
+                            if (fill == 64 && admit()) {
                                 process(64);
-                                fill = 0;
+                                kfill = 0;
                             }
                         }
                         if (self) break;
                     }
                 }
-                if (fill > 0) process(fill);
+                // the rest of stage 1 (a full kept block leaves fewer than 64
+                // points there), then the partial kept block
+                while (fill > 0) {
+                    if (admit()) {
+                        process(64);
+                        kfill = 0;
+                    }
+                }
+                if (kfill > 0) process(kfill);
             }
         }
     }
