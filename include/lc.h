@@ -358,6 +358,35 @@ lc_status lc_map_matrix(const double* X, int32_t P_in, const int32_t* group, con
                         double* Y, void* stream);
 
 /*
+ * Maps for lc_map_vectors / lc_map_matrix (HOST calls: they fill host arrays
+ * and touch no device).  group and weight are HOST arrays of P_in entries,
+ * written; *P_out receives the mapped length.  LC_ERR_INVALID for NULL
+ * pointers or sizes out of range.
+ *
+ * lc_map_multipoles: from the data vector [xi(r, mu) | xi_0 | xi_2 | xi_4]
+ *   (P_in = n_r n_mu + 3 n_r) to the multipoles selected by ell_mask (bit 0:
+ *   l = 0, bit 1: l = 2, bit 2: l = 4; output blocks in increasing l) over
+ *   the r bins [r_lo, r_hi), each output the mean of w adjacent r bins, the
+ *   last group narrower when w does not divide r_hi - r_lo.  w = 1 selects:
+ *   the 540-element vector of Sect. 5.3 (xi_0, xi_2, xi_4 of the 1 Mpc/h
+ *   bins between 20 and 200 Mpc/h); w > 1 re-bins to wider r bins, with the
+ *   wide bin's multipole the mean of its narrow bins' (Table 3).
+ * lc_map_projected: from the data vector of a (r_p, pi) binning (LC_LOS_RPPI,
+ *   n_rp r_p bins x n_pi pi bins, P_in = n_rp n_pi + 3 n_rp) to the projected
+ *   correlation function w_p(r_p) = 2 sum_m xi(r_p, pi_m) (pi_max / n_pi)
+ *   (Sect. 2.3), in the unit of pi_max; P_out = n_rp.
+ * lc_map_rebin_blocks: P_in = n_blocks n; the mean of w adjacent elements
+ *   within each block of n (e.g. the r bins of each multipole), the last
+ *   group of a block narrower when w does not divide n.
+ */
+lc_status lc_map_multipoles(int32_t n_r, int32_t n_mu, int32_t w, int32_t r_lo, int32_t r_hi, int32_t ell_mask,
+                            int32_t* group, double* weight, int32_t* P_out);
+lc_status lc_map_projected(int32_t n_rp, int32_t n_pi, double pi_max, int32_t* group, double* weight,
+                           int32_t* P_out);
+lc_status lc_map_rebin_blocks(int32_t n_blocks, int32_t n, int32_t w, int32_t* group, double* weight,
+                              int32_t* P_out);
+
+/*
  * lc_sample_covariance: the sample covariance over mocks of one estimate
  * (Sect. 2.2): C = sum_n (x_n - mean)(x_n - mean)^T / (N - 1), two-pass.
  *   x          DEVICE double [n_mock][P] (e.g. from lc_xi_split); n_mock >= 2.

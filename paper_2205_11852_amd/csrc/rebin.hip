@@ -220,3 +220,76 @@ extern "C" lc_status lc_map_matrix(const double* X, int32_t P_in, const int32_t*
     if (e != hipSuccess) return fail(LC_ERR_HIP, "map launch failed: %s", hipGetErrorString(e));
     return LC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// maps of the data vector (host): the inputs of lc_map_vectors / lc_map_matrix
+// ---------------------------------------------------------------------------
+
+extern "C" lc_status lc_map_multipoles(int32_t n_r, int32_t n_mu, int32_t w, int32_t r_lo, int32_t r_hi,
+                                       int32_t ell_mask, int32_t* group, double* weight, int32_t* P_out) {
+    clear_error();
+    if (!group || !weight || !P_out) return fail(LC_ERR_INVALID, "group, weight and P_out must not be NULL");
+    if (n_r < 1 || n_mu < 1 || int64_t(n_r) * n_mu > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad n_r = %d / n_mu = %d", n_r, n_mu);
+    if (!(0 <= r_lo && r_lo < r_hi && r_hi <= n_r) || w < 1)
+        return fail(LC_ERR_INVALID, "bad r range [%d, %d) or width %d", r_lo, r_hi, w);
+    if (ell_mask < 1 || ell_mask > 7) return fail(LC_ERR_INVALID, "ell_mask = %d, must select l = 0, 2 or 4", ell_mask);
+    const int32_t P = n_r * n_mu + 3 * n_r;
+    for (int32_t i = 0; i < P; i++) {
+        group[i] = -1;
+        weight[i] = 0.0;
+    }
+    // the output mean of a group of w adjacent r bins (the last group of a
+    // range that w does not divide is narrower)
+    const int32_t n_out = (r_hi - r_lo + w - 1) / w;
+    int32_t j = 0;
+    for (int li = 0; li < 3; li++) {
+        if (!(ell_mask & (1 << li))) continue;
+        for (int32_t k = r_lo; k < r_hi; k++) {
+            const int32_t gk = (k - r_lo) / w;
+            const int32_t size = std::min(w, r_hi - r_lo - gk * w);
+            const int32_t i = n_r * n_mu + li * n_r + k;
+            group[i] = j * n_out + gk;
+            weight[i] = 1.0 / double(size);
+        }
+        j++;
+    }
+    *P_out = j * n_out;
+    return LC_OK;
+}
+
+extern "C" lc_status lc_map_projected(int32_t n_rp, int32_t n_pi, double pi_max, int32_t* group, double* weight,
+                                      int32_t* P_out) {
+    clear_error();
+    if (!group || !weight || !P_out) return fail(LC_ERR_INVALID, "group, weight and P_out must not be NULL");
+    if (n_rp < 1 || n_pi < 1 || int64_t(n_rp) * n_pi > LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad n_rp = %d / n_pi = %d", n_rp, n_pi);
+    if (!(pi_max > 0.0) || !std::isfinite(pi_max)) return fail(LC_ERR_INVALID, "pi_max must be finite and > 0");
+    const int32_t nb = n_rp * n_pi, P = nb + 3 * n_rp;
+    // w_p(r_p) = 2 sum_m xi(r_p, pi_m) dpi with dpi = pi_max / n_pi, xi held
+    // constant within a pi bin
+    const double coef = 2.0 * pi_max / double(n_pi);
+    for (int32_t i = 0; i < P; i++) {
+        group[i] = i < nb ? i / n_pi : -1;
+        weight[i] = i < nb ? coef : 0.0;
+    }
+    *P_out = n_rp;
+    return LC_OK;
+}
+
+extern "C" lc_status lc_map_rebin_blocks(int32_t n_blocks, int32_t n, int32_t w, int32_t* group, double* weight,
+                                         int32_t* P_out) {
+    clear_error();
+    if (!group || !weight || !P_out) return fail(LC_ERR_INVALID, "group, weight and P_out must not be NULL");
+    if (w < 1 || n < 1 || n_blocks < 1 || int64_t(n_blocks) * n > int64_t(4) * LC_MAX_BINS)
+        return fail(LC_ERR_INVALID, "bad block map sizes (%d blocks of %d, width %d)", n_blocks, n, w);
+    const int32_t n_out = (n + w - 1) / w;
+    for (int32_t b = 0; b < n_blocks; b++)
+        for (int32_t k = 0; k < n; k++) {
+            const int32_t gk = k / w;
+            group[b * n + k] = b * n_out + gk;
+            weight[b * n + k] = 1.0 / double(std::min(w, n - gk * w));
+        }
+    *P_out = n_blocks * n_out;
+    return LC_OK;
+}

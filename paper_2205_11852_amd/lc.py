@@ -32,6 +32,7 @@ STATUS_NAMES = {0: "LC_OK", -1: "LC_ERR_INVALID", -2: "LC_ERR_RANGE", -3: "LC_ER
 EXPORTS = ["lc_last_error", "lc_build_cells", "lc_free_cells", "lc_cells_get_info",
            "lc_pair_count_batch", "lc_pair_count_batch_noalloc", "lc_xi_multipoles", "lc_covariance", "lc_xi_split", "lc_sample_covariance", "lc_covcov",
            "lc_autotune", "lc_covariance_general", "lc_rebin_counts", "lc_map_vectors", "lc_map_matrix",
+           "lc_map_multipoles", "lc_map_projected", "lc_map_rebin_blocks",
            "lc_release_caches"]
 
 
@@ -131,6 +132,12 @@ def lib():
     L.lc_pair_count_batch.restype = st
     L.lc_pair_count_batch.argtypes = [vp, vp, i32, ctypes.POINTER(lc_binning), vp, i32,
                                       ctypes.POINTER(lc_tuning), vp, vp]
+    L.lc_map_multipoles.restype = st
+    L.lc_map_multipoles.argtypes = [i32, i32, i32, i32, i32, i32, vp, vp, vp]
+    L.lc_map_projected.restype = st
+    L.lc_map_projected.argtypes = [i32, i32, ctypes.c_double, vp, vp, vp]
+    L.lc_map_rebin_blocks.restype = st
+    L.lc_map_rebin_blocks.argtypes = [i32, i32, i32, vp, vp, vp]
     L.lc_pair_count_batch_noalloc.restype = st
     L.lc_pair_count_batch_noalloc.argtypes = [vp, vp, i32, ctypes.POINTER(lc_binning), vp, i32,
                                               ctypes.POINTER(lc_tuning), vp, vp]
@@ -411,3 +418,31 @@ def lc_release_caches():
 
 
 INF = math.inf
+
+
+def _map_out(P_in: int):
+    return np.full(P_in, -1, dtype=np.int32), np.zeros(P_in, dtype=np.float64), ctypes.c_int32(0)
+
+
+def lc_map_multipoles(n_r: int, n_mu: int, w: int, r_lo: int, r_hi: int, ell_mask: int):
+    """(group, weight, P_out) of the multipole selection / re-binning map."""
+    g, wt, P = _map_out(int(n_r) * int(n_mu) + 3 * int(n_r))
+    _check(lib().lc_map_multipoles(int(n_r), int(n_mu), int(w), int(r_lo), int(r_hi), int(ell_mask),
+                                   g.ctypes.data, wt.ctypes.data, ctypes.byref(P)))
+    return g, wt, int(P.value)
+
+
+def lc_map_projected(n_rp: int, n_pi: int, pi_max: float):
+    """(group, weight, P_out) of the map to w_p(r_p)."""
+    g, wt, P = _map_out(int(n_rp) * int(n_pi) + 3 * int(n_rp))
+    _check(lib().lc_map_projected(int(n_rp), int(n_pi), float(pi_max), g.ctypes.data, wt.ctypes.data,
+                                  ctypes.byref(P)))
+    return g, wt, int(P.value)
+
+
+def lc_map_rebin_blocks(n_blocks: int, n: int, w: int):
+    """(group, weight, P_out) of the within-block averaging map."""
+    g, wt, P = _map_out(int(n_blocks) * int(n))
+    _check(lib().lc_map_rebin_blocks(int(n_blocks), int(n), int(w), g.ctypes.data, wt.ctypes.data,
+                                     ctypes.byref(P)))
+    return g, wt, int(P.value)

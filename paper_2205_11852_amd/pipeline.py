@@ -57,59 +57,34 @@ def plan_direct_tasks(mocks: Sequence[int], subsets: Sequence[int]) -> Tuple[np.
 def multipole_map(n_r: int, n_mu: int, w: int = 1, r_lo: int = 0, r_hi: Optional[int] = None,
                   ells: Sequence[int] = (0, 2, 4)) -> Tuple[np.ndarray, np.ndarray, int]:
     """Map (group, weight, P_out) for lc_map_vectors / lc_map_matrix from the
-    data vector [xi(r, mu) | xi_0 | xi_2 | xi_4] to the multipoles `ells` over
-    r bins [r_lo, r_hi), each output the mean of w adjacent r bins (the last
-    group of a range that w does not divide is narrower).  w = 1 selects, as
-    the 540-element vector of the paper's slabs (r = 20 .. 200 Mpc/h in
-    1 Mpc/h bins) does; w > 1 re-bins to wider bins (Table 3)."""
+    data vector to the multipoles `ells` (increasing) over r bins
+    [r_lo, r_hi), each output the mean of w adjacent r bins; built by the
+    library (lc_map_multipoles).  w = 1 selects (the paper's 540-element
+    vector); w > 1 re-bins (Table 3)."""
     r_hi = n_r if r_hi is None else int(r_hi)
+    ells = list(ells)
+    if ells != sorted(set(ells)) or any(e not in (0, 2, 4) for e in ells) or not ells:
+        raise ValueError("ells must be an increasing subset of (0, 2, 4)")
     if not (0 <= r_lo < r_hi <= n_r) or w < 1:
         raise ValueError("bad r range [%d, %d) or width %d" % (r_lo, r_hi, w))
-    P = n_r * n_mu + 3 * n_r
-    group = np.full(P, -1, dtype=np.int32)
-    weight = np.zeros(P)
-    n_out = (r_hi - r_lo + w - 1) // w
-    for j, ell in enumerate(ells):
-        li = (0, 2, 4).index(ell)
-        for k in range(r_lo, r_hi):
-            gk = (k - r_lo) // w
-            size = min(w, r_hi - r_lo - gk * w)
-            i = n_r * n_mu + li * n_r + k
-            group[i] = j * n_out + gk
-            weight[i] = 1.0 / size
-    return group, weight, len(ells) * n_out
+    mask = sum(1 << (0, 2, 4).index(e) for e in ells)
+    return lc.lc_map_multipoles(n_r, n_mu, w, r_lo, r_hi, mask)
 
 
 def projected_map(n_rp: int, n_pi: int, pi_max: float) -> Tuple[np.ndarray, np.ndarray, int]:
     """Map (group, weight, P_out) from the data vector of a (r_p, pi)
-    binning (LC_LOS_RPPI: xi(r_p, pi) r_p-major, then the unused multipole
-    part) to the projected correlation function
-    w_p(r_p) = 2 sum_m xi(r_p, pi_m) (pi_max / n_pi), in the unit of pi_max."""
-    P = n_rp * n_pi + 3 * n_rp
-    group = np.full(P, -1, dtype=np.int32)
-    weight = np.zeros(P)
-    nb = n_rp * n_pi
-    group[:nb] = np.repeat(np.arange(n_rp, dtype=np.int32), n_pi)
-    weight[:nb] = 2.0 * pi_max / n_pi
-    return group, weight, n_rp
+    binning to w_p(r_p), in the unit of pi_max; built by the library
+    (lc_map_projected)."""
+    return lc.lc_map_projected(n_rp, n_pi, pi_max)
 
 
 def block_rebin_map(n_blocks: int, n: int, w: int) -> Tuple[np.ndarray, np.ndarray, int]:
     """Map (group, weight, P_out) that averages w adjacent elements within
-    each of n_blocks consecutive blocks of n (e.g. the r bins of each
-    multipole); the last group of a block is narrower when w does not
-    divide n."""
+    each of n_blocks consecutive blocks of n; built by the library
+    (lc_map_rebin_blocks)."""
     if w < 1 or n < 1 or n_blocks < 1:
         raise ValueError("bad block map sizes")
-    n_out = (n + w - 1) // w
-    group = np.empty(n_blocks * n, dtype=np.int32)
-    weight = np.empty(n_blocks * n)
-    for j in range(n_blocks):
-        for k in range(n):
-            gk = k // w
-            group[j * n + k] = j * n_out + gk
-            weight[j * n + k] = 1.0 / min(w, n - gk * w)
-    return group, weight, n_blocks * n_out
+    return lc.lc_map_rebin_blocks(n_blocks, n, w)
 
 
 class Pipeline:

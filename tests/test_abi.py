@@ -245,3 +245,19 @@ def test_map_calls_reject_bad_arguments(L):
     assert L.lc_map_matrix(0x1000, 4, bad.ctypes.data, w.ctypes.data, 2, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_map_matrix(None, 4, g.ctypes.data, w.ctypes.data, 2, 0x2000, None) == lc.LC_ERR_INVALID
     assert L.lc_map_matrix(0x1000, 4, g.ctypes.data, w.ctypes.data, 2, 0x1000, None) == lc.LC_ERR_INVALID
+
+
+def test_map_builders_reject_bad_arguments(L):
+    g = np.zeros(64, dtype=np.int32)
+    w = np.zeros(64)
+    P = ctypes.c_int32(0)
+    assert L.lc_map_multipoles(4, 5, 1, 0, 4, 7, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_OK
+    assert P.value == 12
+    assert L.lc_map_multipoles(4, 5, 1, 3, 2, 7, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_multipoles(4, 5, 0, 0, 4, 7, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_multipoles(4, 5, 1, 0, 4, 8, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_multipoles(4, 5, 1, 0, 4, 7, None, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_projected(4, 5, 0.0, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_projected(4, 5, float("inf"), g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_rebin_blocks(3, 0, 2, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+    assert L.lc_map_rebin_blocks(3, 4, 0, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID

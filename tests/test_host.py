@@ -1,6 +1,7 @@
-"""Host-side logic of the binding (CPU only): the task planner and the map
-builders that feed lc_map_vectors / lc_map_matrix, checked against the
-oracle's definitions of the quantities they select or combine."""
+"""Host-side logic (CPU only): the binding's task planner, and the library's
+map builders (lc_map_multipoles, lc_map_projected, lc_map_rebin_blocks: host
+calls of liblc that feed lc_map_vectors / lc_map_matrix), checked against
+the oracle's definitions of the quantities they select or combine."""
 import numpy as np
 import pytest
 
@@ -54,6 +55,20 @@ def test_multipole_map_rebins_by_averaging(oracle_mod, w):
     assert y.shape == (3, n_out)
     for j in range(n_out):
         assert np.allclose(y[:, j], mp[:, j * w:(j + 1) * w].mean(axis=1), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("ells", [(2,), (0, 4), (4,), (0, 2)])
+def test_multipole_map_selects_subsets(oracle_mod, ells):
+    n_r, n_mu = 12, 7
+    xi = np.random.default_rng(len(ells)).normal(size=(n_r, n_mu))
+    g, wt, P = pipeline.multipole_map(n_r, n_mu, 1, 2, 11, ells)
+    assert P == 9 * len(ells)
+    y = oracle_mod.map_vectors(oracle_mod.data_vector(xi), g, wt, P).reshape(len(ells), 9)
+    mp = oracle_mod.multipoles(xi)
+    for j, ell in enumerate(ells):
+        assert np.array_equal(y[j], mp[(0, 2, 4).index(ell), 2:11])
+    with pytest.raises(ValueError):
+        pipeline.multipole_map(n_r, n_mu, 1, 0, n_r, (4, 0))
 
 
 def test_block_rebin_map_averages_within_blocks(oracle_mod):
