@@ -165,7 +165,18 @@ typedef struct {
                                  the block histogram out to counts (the overflow guard).
                                  0 = the largest safe value, 2^32 / waves_per_block, which keeps
                                  every uint32 bin from wrapping; a small value forces the guard */
+    int32_t queue_order;      /* order of the work queue of a persistent launch (tasks are taken
+                                 largest first, by n_a n_b, halved for auto pairs):
+                                 LC_QUEUE_XCD_RANGES (0, default): eight contiguous ranges of
+                                 equal cost, one per XCD, so an XCD's L2 serves neighbouring
+                                 tasks; LC_QUEUE_XCD_DEALT: the cost order dealt to the eight
+                                 XCD queues in turn; LC_QUEUE_SHARED: one queue for every block.
+                                 A block whose queue is empty takes work from the next one */
 } lc_tuning;
+
+#define LC_QUEUE_XCD_RANGES 0
+#define LC_QUEUE_XCD_DEALT  1
+#define LC_QUEUE_SHARED     2
 
 /*
  * lc_pair_count_batch: add the (r, mu) pair counts of every task.
@@ -456,7 +467,10 @@ typedef struct {
  * replaces the incumbent only when it is more than 2% faster on the sample
  * (waves per block keep the default: a sample of the tasks predicts small
  * differences poorly for the whole batch).  Each is timed with HIP events over `sample_tasks` tasks
- * spread evenly over the list (one untimed launch, then two timed).
+ * spread evenly over the list (one untimed launch, then two timed).  Last, the three
+ * queue orders (lc_tuning.queue_order) are timed on the whole batch, one launch each, on the
+ * chosen mesh (an order changes the launch's tail, which a sample does not show); skipped when
+ * the sample is the whole batch.
  *   xyz, n_total, cat_offsets, n_cat, b   as for lc_build_cells.
  *   tasks     HOST [n_tasks], as for lc_pair_count_batch.
  *   sample_tasks  tasks to time (<= 0: 64).

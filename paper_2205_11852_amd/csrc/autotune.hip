@@ -7,7 +7,9 @@
 // gather.  Rather than model that trade on a given catalogue set, the tuner
 // measures it: it builds candidate meshes, times the persistent launch on an
 // evenly spread sample of the tasks with HIP events, and keeps the fastest.
-// Results are cached per device and configuration for the life of the process.
+// Last, on the chosen mesh and launch shape, the order of the work queue is
+// timed on the whole batch.  Results are cached per device and configuration
+// for the life of the process.
 
 #include <algorithm>
 #include <cmath>
@@ -53,12 +55,13 @@ std::string tune_key(int device, const lc_binning* b, const int64_t* off, int32_
     return buf;
 }
 
-// Time `reps` launches of the sample (after one untimed launch); ms per launch.
+// Time `reps` launches of the sample (after one untimed launch unless
+// warm = false); ms per launch.
 lc_status time_launch(const lc_cells* cells, const std::vector<lc_task>& sample, const lc_binning* b,
                       uint64_t* counts, const lc_tuning& tune, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
-                      int reps, double* ms) {
+                      int reps, double* ms, bool warm = true) {
     const int32_t n = int32_t(sample.size());
-    LC_TRY(lc_pair_count_batch(cells, sample.data(), n, b, counts, LC_PERSISTENT, &tune, nullptr, s));
+    if (warm) LC_TRY(lc_pair_count_batch(cells, sample.data(), n, b, counts, LC_PERSISTENT, &tune, nullptr, s));
     LC_TRY_HIP(hipEventRecord(e0, s));
     for (int r = 0; r < reps; r++)
         LC_TRY(lc_pair_count_batch(cells, sample.data(), n, b, counts, LC_PERSISTENT, &tune, nullptr, s));
@@ -203,6 +206,36 @@ extern "C" lc_status lc_autotune(const int32_t* xyz, int64_t n_total, const int6
             }
             lc_free_cells(c);
         }
+    }
+    // stage 3: the order of the work queue, on the whole batch (what an order
+    // changes is the launch's tail, which a sample of the tasks does not
+    // have); skipped when the sample is the whole batch
+    if (st == LC_OK && ns < n_tasks) {
+        uint64_t* all = nullptr;
+        st = dev_alloc((void**)&all, size_t(n_tasks) * nbins * sizeof(uint64_t), s);
+        lc_cells* c = nullptr;
+        if (st == LC_OK) st = lc_build_cells(xyz, n_total, cat_offsets, n_cat, b, &best_mesh, s, &c);
+        if (st == LC_OK) {
+            std::vector<lc_task> every(tasks, tasks + n_tasks);
+            double base_ms = 0.0;
+            for (int q : {LC_QUEUE_XCD_RANGES, LC_QUEUE_XCD_DEALT, LC_QUEUE_SHARED}) {
+                lc_tuning tn = best.tune;
+                tn.queue_order = q;
+                double ms = 0.0;
+                // the default order first (its untimed launch also warms the caches)
+                st = time_launch(c, every, b, all, tn, s, e0, e1, 1, &ms, q == LC_QUEUE_XCD_RANGES);
+                if (st != LC_OK) break;
+                tried++;
+                if (q == LC_QUEUE_XCD_RANGES) {
+                    base_ms = ms;
+                } else if (ms < base_ms * (1.0 - kGain)) {
+                    base_ms = ms;
+                    best.tune.queue_order = q;
+                }
+            }
+        }
+        if (c) lc_free_cells(c);
+        dev_free(all, s);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);

@@ -1114,6 +1114,9 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     if (n_items >= (int64_t(1) << 31))
         return fail(LC_ERR_OVERFLOW, "%lld work items exceed the 31-bit queue", (long long)n_items);
     const bool per_task = (mode & LC_PER_TASK) != 0;
+    const int qorder = tune ? tune->queue_order : LC_QUEUE_XCD_RANGES;
+    if (qorder != LC_QUEUE_XCD_RANGES && qorder != LC_QUEUE_XCD_DEALT && qorder != LC_QUEUE_SHARED)
+        return fail(LC_ERR_INVALID, "queue_order = %d is not LC_QUEUE_XCD_RANGES, _DEALT or _SHARED", qorder);
     p.single_task = -1;
     if (per_task) {
         // one queue holds the task's items; the other queues start empty
@@ -1123,7 +1126,7 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
         pl.task_blocks.resize(n_tasks);
         for (int t = 0; t < n_tasks; t++)
             pl.task_blocks[t] = int(std::max<int64_t>(1, std::min<int64_t>(p.items_per_task, pl.blocks)));
-    } else {
+    } else if (qorder == LC_QUEUE_XCD_RANGES) {
         // split the ordered tasks into kXcd contiguous ranges of equal cost;
         // blocks of XCD x start on range x and move on when it is empty
         double total = 0;
@@ -1136,6 +1139,24 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
             while (x < kXcd && acc >= total * x / kXcd) p.qstart[x++] = uint32_t(int64_t(s + 1) * p.items_per_task);
         }
         for (; x <= kXcd; x++) p.qstart[x] = uint32_t(n_items);
+        pl.n_queue = kXcd;
+    } else if (qorder == LC_QUEUE_XCD_DEALT) {
+        // task s of the cost order goes to queue s mod kXcd: every queue
+        // starts with large tasks and holds tasks of every size
+        std::vector<int32_t> dealt;
+        dealt.reserve(n_tasks);
+        p.qstart[0] = 0;
+        for (int x = 0; x < kXcd; x++) {
+            for (int s = x; s < n_tasks; s += kXcd) dealt.push_back(order[s]);
+            p.qstart[x + 1] = uint32_t(int64_t(dealt.size()) * p.items_per_task);
+        }
+        order.swap(dealt);
+        pl.n_queue = kXcd;
+    } else {
+        // one queue in cost order: blocks of the other XCDs find theirs empty
+        // and move on to it
+        p.qstart[0] = 0;
+        for (int x = 1; x <= kXcd; x++) p.qstart[x] = uint32_t(n_items);
         pl.n_queue = kXcd;
     }
     // staged block: tasks, order, stencil, squared edges, zeroed queue counters

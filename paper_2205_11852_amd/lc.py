@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(HERE, "liblc.so")
 LC_OK, LC_ERR_INVALID, LC_ERR_RANGE, LC_ERR_OVERFLOW, LC_ERR_HIP, LC_ERR_NOMEM = 0, -1, -2, -3, -4, -5
 LC_LOS_Z, LC_LOS_MID, LC_LOS_RPPI = 0, 1, 2
 LC_PERSISTENT, LC_PER_TASK, LC_GRAPH, LC_FORCE_EXACT = 0, 1, 2, 4
+LC_QUEUE_XCD_RANGES, LC_QUEUE_XCD_DEALT, LC_QUEUE_SHARED = 0, 1, 2
 LC_FP64, LC_FP32_MFMA, LC_FP32_MFMA_CHECKED, LC_ACC32 = 0, 1, 2, 8
 LC_MAX_BINS, LC_MAX_NMU = 32768, 1024
 LC_NOALLOC_PLAN_BYTES = 1 << 20
@@ -59,7 +60,7 @@ class lc_task(ctypes.Structure):
 class lc_tuning(ctypes.Structure):
     _fields_ = [("cells_per_item", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("flush_limit", ctypes.c_int32)]
+                ("flush_limit", ctypes.c_int32), ("queue_order", ctypes.c_int32)]
 
 
 class lc_mesh_opts(ctypes.Structure):
@@ -83,7 +84,7 @@ class lc_autotune_result(ctypes.Structure):
         t = self.tune
         return {"cell_units": self.cell_units, "sub": self.sub,
                 "tune": {"cells_per_item": t.cells_per_item, "waves_per_block": t.waves_per_block,
-                         "blocks_per_cu": t.blocks_per_cu, "chunk": t.chunk},
+                         "blocks_per_cu": t.blocks_per_cu, "chunk": t.chunk, "queue_order": t.queue_order},
                 "sample_ms": self.sample_ms, "n_tried": self.n_tried, "sample_tasks": self.sample_tasks,
                 "cached": bool(self.cached)}
 
@@ -292,7 +293,7 @@ def _pair_count_args(cells, tasks, binning, counts, tune):
     if tune:
         tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
                        int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)),
-                       int(tune.get("flush_limit", 0)))
+                       int(tune.get("flush_limit", 0)), int(tune.get("queue_order", 0)))
     return t, tn
 
 

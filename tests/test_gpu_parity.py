@@ -117,13 +117,22 @@ def test_c1_per_mock_baseline_identical(c1, torch):
                                   dict(waves_per_block=8, blocks_per_cu=1), dict(waves_per_block=2),
                                   dict(chunk=4), dict(chunk=12), dict(chunk=32), dict(chunk=64),
                                   dict(chunk=20, cells_per_item=3), dict(chunk=128), dict(chunk=256),
-                                  dict(waves_per_block=16), dict(waves_per_block=16, chunk=64, cells_per_item=2)])
+                                  dict(waves_per_block=16), dict(waves_per_block=16, chunk=64, cells_per_item=2),
+                                  dict(queue_order=1), dict(queue_order=2), dict(queue_order=2, waves_per_block=16),
+                                  dict(queue_order=1, cells_per_item=3, chunk=64)])
 def test_c1_tunings_identical(c1, torch, tune):
     pl = c1["pl"]
     _say("[c1] tune", tune)
     pl.count(tune=tune)
     torch.cuda.synchronize()
     assert np.array_equal(pl.counts_host(), c1["ref"])
+
+
+def test_bad_queue_order_is_refused(c1, lcmod, torch):
+    pl = c1["pl"]
+    with pytest.raises(lcmod.LcError) as ei:
+        pl.count(tune=dict(queue_order=3))
+    assert ei.value.status == lcmod.LC_ERR_INVALID and "queue_order" in str(ei.value)
 
 
 def test_c1_autotuned_counts_identical(c1, torch):
