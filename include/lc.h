@@ -110,9 +110,9 @@ typedef struct {
  *   out          receives the mesh; free with lc_free_cells.
  * Synchronises `stream` (once for a periodic box, twice for open geometry:
  * the bounding box, then the device range-check word).  A point outside the
- * geometry returns LC_ERR_RANGE and no mesh.  With LC_LOS_MID the mesh also
- * keeps the points' absolute coordinates (twice the point memory) and every
- * catalogue must hold fewer than 2^28 points (else LC_ERR_OVERFLOW); pair
+ * geometry returns LC_ERR_RANGE and no mesh.  Every catalogue must hold
+ * fewer than 2^28 points (else LC_ERR_OVERFLOW).  With LC_LOS_MID the mesh
+ * also keeps the points' absolute coordinates (twice the point memory); pair
  * counting with LC_LOS_MID needs such a mesh.
  */
 lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,

@@ -343,12 +343,10 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
             return fail(LC_ERR_INVALID, "cat_offsets decreasing at %d", c);
     if (cat_offsets[n_cat] != n_total) return fail(LC_ERR_INVALID, "cat_offsets[n_cat] != n_total");
     if (n_total >= (int64_t(1) << 40)) return fail(LC_ERR_OVERFLOW, "n_total too large");
-    if (b->los == LC_LOS_MID)
-        for (int32_t c = 0; c < n_cat; c++)
-            if (cat_offsets[c + 1] - cat_offsets[c] >= kMidMaxCatalogue)
-                return fail(LC_ERR_OVERFLOW, "catalogue %d holds %lld points; the midpoint line of sight "
-                                             "allows fewer than %lld per catalogue", c,
-                            (long long)(cat_offsets[c + 1] - cat_offsets[c]), (long long)kMidMaxCatalogue);
+    for (int32_t c = 0; c < n_cat; c++)
+        if (cat_offsets[c + 1] - cat_offsets[c] >= kMaxCatalogue)
+            return fail(LC_ERR_OVERFLOW, "catalogue %d holds %lld points; a catalogue holds fewer than %lld",
+                        c, (long long)(cat_offsets[c + 1] - cat_offsets[c]), (long long)kMaxCatalogue);
 
     DeviceCtx* ctx;
     LC_TRY(get_ctx(&ctx));

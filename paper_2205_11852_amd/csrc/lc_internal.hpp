@@ -14,10 +14,11 @@
 
 namespace lc {
 
-// Midpoint line of sight: points per catalogue stay below 2^28, so that a
-// pair's i index within its catalogue (kept in a 32-bit queue slot) times
-// 12 bytes is a 32-bit offset into the catalogue's absolute coordinates.
-constexpr int64_t kMidMaxCatalogue = int64_t(1) << 28;
+// Points per catalogue stay below 2^28, so that a point's index within its
+// catalogue times 12 bytes is a 32-bit byte offset: the pair kernel gathers
+// points by such offsets, and the midpoint line of sight keeps them in a
+// 32-bit queue slot.
+constexpr int64_t kMaxCatalogue = int64_t(1) << 28;
 
 // ---------------------------------------------------------------------------
 // errors

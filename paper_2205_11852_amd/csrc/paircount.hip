@@ -220,6 +220,7 @@ struct WaveState {
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
+    const float* pj;      // points of the task's j catalogue (wave-uniform)
     const float* ai;      // midpoint: absolute coordinates of the task's j catalogue (wave-uniform)
     uint32_t ai_last;     // midpoint: byte offset of that catalogue's last point (clamp of queued offsets)
     int64_t b0;           // midpoint: global index of the catalogue's first point
@@ -567,6 +568,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     unsigned* ctl = reinterpret_cast<unsigned*>(smem) + p.hist_stride;
     WaveState w;
     w.hist = reinterpret_cast<unsigned*>(smem);
+    w.pj = pts;
     w.ai = apts;
     w.ai_last = 0;
     w.b0 = 0;
@@ -620,13 +622,16 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
             }
             w.since_flush = 0;
             cur_task = task;
+            // the task's j catalogue: points are gathered by their byte
+            // offset from its first point (catalogues hold fewer than 2^28
+            // points); midpoint entries queued from here on hold such
+            // offsets (both queues were binned above)
+            const int64_t cat0 = int64_t(tasks[task].y) * p.ncell * p.nsub;
+            const int64_t b0 = uniform64(cs[cat0]);
+            w.b0 = b0;
+            w.pj = pts + 3 * b0;
             if (LOS == 1) {
-                // entries queued from here on hold byte offsets in the new
-                // task's j catalogue (both queues were binned above)
-                const int64_t cat0 = int64_t(tasks[task].y) * p.ncell * p.nsub;
-                const int64_t b0 = uniform64(cs[cat0]);
                 const int64_t b1 = uniform64(cs[cat0 + p.ncell * p.nsub]);
-                w.b0 = b0;
                 w.ai = apts + 3 * b0;
                 w.ai_last = uint32_t(max(b1 - b0, int64_t(1)) - 1) * 12u;
             }
@@ -831,13 +836,20 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         while (jb < je) {
                             // lanes [fill, fill + take) take points jb, jb + 1, ...
                             const int take = int(min(je - jb, int64_t(64 - fill)));
+                            // lane's point: jb + lane - fill, as a byte offset in the
+                            // j catalogue (and, for the i cell itself, as an index
+                            // relative to the chunk start: both below 2^31)
+                            const int32_t jo = int32_t(jb - w.b0) - fill;
+                            const int32_t io = self ? int32_t(jb - ib) - fill : 0;
                             if (lane >= fill && lane < fill + take) {
-                                const int64_t j = jb + (lane - fill);
-                                sx = pts[3 * j] + dox;
-                                sy = pts[3 * j + 1] + doy;
-                                sz = pts[3 * j + 2] + doz;
-                                srel = self ? int(min(j - ib, int64_t(INT_MAX))) : INT_MAX;
-                                if (LOS == 1) sw = __int_as_float(int(uint32_t(j - w.b0) * 12u));
+                                const uint32_t off = uint32_t(lane + jo) * 12u;
+                                const float* q = reinterpret_cast<const float*>(
+                                    reinterpret_cast<const char*>(w.pj) + off);
+                                sx = q[0] + dox;
+                                sy = q[1] + doy;
+                                sz = q[2] + doz;
+                                srel = self ? lane + io : INT_MAX;
+                                if (LOS == 1) sw = __int_as_float(int(off));
                             }
                             fill += take;
                             jb += take;

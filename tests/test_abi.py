@@ -97,13 +97,14 @@ def test_build_cells_rejects_bad_layout(L):
     assert "xyz" in lc.last_error()
 
 
-def test_build_cells_midpoint_catalogue_limit(L):
-    """Midpoint meshes hold fewer than 2^28 points per catalogue (checked on
-    the host before any device work)."""
-    b = _binning(periodic=False, los=lc.LC_LOS_MID)
+@pytest.mark.parametrize("los", [lc.LC_LOS_MID, lc.LC_LOS_Z])
+def test_build_cells_catalogue_limit(L, los):
+    """A catalogue holds fewer than 2^28 points (checked on the host before
+    any device work), whatever the line of sight."""
+    b = _binning(periodic=False, los=los)
     n = 1 << 28
     assert _build_status(L, b, n_total=n + 5, offsets=(0, 5, n + 5)) == lc.LC_ERR_OVERFLOW
-    assert "midpoint" in lc.last_error()
+    assert "catalogue 1" in lc.last_error()
 
 
 def test_pair_count_rejects_bad_arguments(L):
