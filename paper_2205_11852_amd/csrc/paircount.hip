@@ -216,7 +216,30 @@ __device__ __forceinline__ int exact_bin(int64_t sx, int64_t sy, int64_t sz, int
     return k * n_mu + m;
 }
 
+// A wave-uniform value held in a vector register.  The kernel keeps more
+// live scalars than the scalar register file holds, and a spilled scalar is
+// reloaded with v_readlane, one vector instruction per use; the constants of
+// the innermost loops cost nothing extra as vector operands.
+__device__ __forceinline__ float vreg(float x) {
+    float r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+__device__ __forceinline__ uint32_t vreg(uint32_t x) {
+    uint32_t r;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(r) : "s"(x));
+    return r;
+}
+
+// Constants of the binning of queued pairs held in vector registers (the
+// midpoint kernel; the others read them from the parameters).
+struct BinConst {
+    float mu_shift, ok_m;
+    uint32_t nmu4;
+};
+
 struct WaveState {
+    BinConst bc;
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
@@ -257,9 +280,9 @@ __device__ __forceinline__ void wave_sync_lds() {
 // integer rule later.  d2 = 0 (and q = 0) give NaN or clamped estimates that
 // fail the test, so every value stays finite.  (A bound below 0 sends every
 // pair to the integer rule.)
-template <int LOS, bool UNIFORM, bool HAS_E0>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL>
 __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
-                                             const PcParams& p, float& fm, float& fr) {
+                                             const PcParams& p, const BinConst& bc, float& fm, float& fr) {
     // Each estimate is shifted down by its margin eps inside the FMA that
     // forms it, x' = x - eps.  Then fract(x') < 1 - 2 eps (one compare)
     // holds only when x lies in (floor(x') + eps', floor(x') + 1 - eps') with
@@ -280,12 +303,13 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
         // l = x_i + x_j = 2 x_j - s from the j point's absolute coordinates;
-        // e.w holds their byte offset in the task's j catalogue, clamped so
-        // that a lane past the drained entries (masked by the caller) reads
-        // inside the catalogue.  l, p = s.l and q = l.l in float32, within
-        // the error bound that make_plan's mu margin covers.  d2 = 0 or
-        // q = 0 give an infinite rsq and a NaN estimate, which fails.
-        const uint32_t off = min(uint32_t(__float_as_int(e.w)), ai_last);
+        // e.w holds their byte offset in the task's j catalogue.  A full
+        // drain reads 64 entries of the current task; a partial one clamps
+        // the offset so that a lane past the drained entries (masked by the
+        // caller) reads inside the catalogue.  l, p = s.l and q = l.l in
+        // float32, within the error bound that make_plan's mu margin covers.
+        // d2 = 0 or q = 0 give an infinite rsq and a NaN estimate, which fails.
+        const uint32_t off = FULL ? uint32_t(__float_as_int(e.w)) : min(uint32_t(__float_as_int(e.w)), ai_last);
         const float* xj = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ai) + off);
         const float lx = fmaf(2.0f, xj[0], -e.x);
         const float ly = fmaf(2.0f, xj[1], -e.y);
@@ -294,7 +318,7 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         const float Q = fmaf(lx, lx, fmaf(ly, ly, lz * lz));
         d2f = fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z));
         rs = __builtin_amdgcn_rsqf(d2f);
-        u = fmaf(fabsf(P) * (rs * p.nmuf), __builtin_amdgcn_rsqf(Q), -p.mu_shift);
+        u = fmaf(fabsf(P) * (rs * p.nmuf), __builtin_amdgcn_rsqf(Q), -bc.mu_shift);
     }
     // |mu| n_mu <= n_mu exactly; an estimate within eps_m of n_mu (mu near 1)
     // fails the test, so m < n_mu whenever the pair is kept
@@ -310,7 +334,7 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         fr = __builtin_amdgcn_fractf(t);
     }
     // 24-bit multiply-add: k < n_r and 4 n_mu are far below 2^24
-    return __umul24(k, p.nmu4) + (m << 2);
+    return __umul24(k, LOS == 1 ? bc.nmu4 : p.nmu4) + (m << 2);
 }
 
 // Histogram slot of one queued pair by the integer rule (discard slot when it
@@ -367,14 +391,16 @@ __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t
 // first + lane stays inside the queue (a full drain starts at most 63
 // entries in, since the queue held fewer than 64 before the last append of
 // at most 64; a partial drain starts at 0), and lanes past n are masked.
-template <int LOS, bool UNIFORM, bool HAS_E0>
+// FULL: n = 64, so every slot read holds an entry of the current task.
+template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL>
 __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = qt - n;
     const float4 e = w.qa[first + lane];
     float fm, fr;
-    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0>(e, w.ai, w.ai_last, p, fm, fr);
+    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0, FULL>(e, w.ai, w.ai_last, p, w.bc, fm, fr);
+    const float ok_m = LOS == 1 ? w.bc.ok_m : p.ok_m;
     const bool live = uint32_t(lane) < n;
     const unsigned long long live_mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
     // The lanes the estimates do not decide, from the two compares' lane
@@ -383,8 +409,8 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
     // mask the histogram add; a ballot of the combined bool would copy the
     // mask through a vector register first.
     const unsigned long long xb =
-        live_mask & ~(__builtin_amdgcn_fcmpf(fm, p.ok_m, 4) & __builtin_amdgcn_fcmpf(fr, p.ok_r, 4));
-    const bool ok = (fm < p.ok_m) && (fr < p.ok_r);
+        live_mask & ~(__builtin_amdgcn_fcmpf(fm, ok_m, 4) & __builtin_amdgcn_fcmpf(fr, p.ok_r, 4));
+    const bool ok = (fm < ok_m) && (fr < p.ok_r);
     if (ok && live)
         __hip_atomic_fetch_add(lds_u32_at(addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (xb) {
@@ -406,7 +432,7 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
 template <int LOS, bool UNIFORM, bool HAS_E0>
 __device__ __forceinline__ void drain_all(WaveState& w, int lane, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
-    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0>(w, lane, w.qtail, w.qtail, p, xt);
+    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0, false>(w, lane, w.qtail, w.qtail, p, xt);
     if (w.xn) w.xn = drain_exact<LOS, UNIFORM>(w, lane, w.xn, w.xn, xt);
 }
 
@@ -490,7 +516,7 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
                 make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
-        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0>(w, lane, 64, qt, p, xt);
+        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0, true>(w, lane, 64, qt, p, xt);
     }
     return qt;
 }
@@ -572,8 +598,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     w.ai = apts;
     w.ai_last = 0;
     w.b0 = 0;
-    w.qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
-    w.qa = reinterpret_cast<float4*>(smem + w.qbyte);
+    const uint32_t qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
+    w.qa = reinterpret_cast<float4*>(smem + qbyte);
+    // The midpoint kernel holds the most scalars (its j catalogue's absolute
+    // coordinates): there these constants go to vector registers; the other
+    // kernels keep them scalar, where their vector registers are the scarcer.
+    if (LOS == 1) {
+        w.qbyte = vreg(qbyte);
+        w.bc.mu_shift = vreg(p.mu_shift);
+        w.bc.ok_m = vreg(p.ok_m);
+        w.bc.nmu4 = vreg(p.nmu4);
+    } else {
+        w.qbyte = qbyte;
+    }
     w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kX;
     w.xn = 0;
     w.qtail = 0;
