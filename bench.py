@@ -212,6 +212,8 @@ def covariance_precision(args, torch, lc) -> dict:
     t = {}
     reps = {}
     for name, prec, checked in (("fp32_mfma", lc.LC_FP32_MFMA, lc.LC_FP32_MFMA_CHECKED),
+                                ("fp32_mfma_acc32", lc.LC_FP32_MFMA | lc.LC_ACC32,
+                                 lc.LC_FP32_MFMA_CHECKED | lc.LC_ACC32),
                                 ("fp64", lc.LC_FP64, lc.LC_FP64)):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         a.record(stream)
@@ -222,11 +224,18 @@ def covariance_precision(args, torch, lc) -> dict:
         # the report: the check of C^LC, and for float32 its float64 twin's errors
         reps[name] = pl.covariance(checked, report=True)
     r32, r64 = reps["fp32_mfma"], reps["fp64"]
-    eig = []
-    for blk in range(2):
-        scale = max(abs(r64["min_eig"][blk]), abs(r64["max_eig"][blk]))
-        eig.append(max(abs(r32["min_eig"][blk] - r64["min_eig"][blk]),
-                       abs(r32["max_eig"][blk] - r64["max_eig"][blk])) / scale)
+
+    def eig_err(r):
+        e = []
+        for blk in range(2):
+            scale = max(abs(r64["min_eig"][blk]), abs(r64["max_eig"][blk]))
+            e.append(max(abs(r["min_eig"][blk] - r64["min_eig"][blk]),
+                         abs(r["max_eig"][blk] - r64["max_eig"][blk])) / scale)
+        return e
+
+    eig = eig_err(r32)
+    r32a = reps["fp32_mfma_acc32"]
+    eig_a = eig_err(r32a)
     return {"workload": "c5: %d mocks x Poisson(%g), %g Mpc/h periodic box, %d x %d randoms, %d x %d bins, P = %d"
                         % (wl.n_mock, wl.n_mean, wl.box_mpc, wl.n_subsets, wl.subset_size, wl.n_r, wl.n_mu,
                            pl.binning.P),
@@ -235,6 +244,13 @@ def covariance_precision(args, torch, lc) -> dict:
                                                           "A": r32["rel_frob_vs_fp64"][1],
                                                           "B": r32["rel_frob_vs_fp64"][2]},
             "max_eig_error_rel": {"xi_block": eig[0], "multipole_block": eig[1]},
+            "fp32_accumulation_over_all_mocks": {
+                "note": "float32 MFMA products accumulated in float32 over all %d mocks (LC_ACC32) instead of "
+                        "float32 blocks of 256 mocks summed in float64" % wl.n_mock,
+                "rel_frob_fp32_vs_fp64": {"C": r32a["rel_frob_vs_fp64"][0], "A": r32a["rel_frob_vs_fp64"][1],
+                                          "B": r32a["rel_frob_vs_fp64"][2]},
+                "max_eig_error_rel": {"xi_block": eig_a[0], "multipole_block": eig_a[1]},
+                "covariance_ms": t["fp32_mfma_acc32"]},
             "report_fp32": r32, "report_fp64": r64}
 
 
@@ -364,42 +380,46 @@ def main():
     }
 
     if not args.no_per_mock:
-        log("[bench] per-mock baseline")
-        pl.count()
-        torch.cuda.synchronize()
-        ref = pl.counts.clone()
-        t0 = time.perf_counter()
-        pl.count()
-        torch.cuda.synchronize()
-        t_batched = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        pl.count_per_mock()
-        torch.cuda.synchronize()
-        t_per_mock = time.perf_counter() - t0
-        same = bool(torch.equal(ref, pl.counts))
-        out["batched_vs_per_mock"] = {"workload": wl.name, "batched_s": t_batched, "per_mock_s": t_per_mock,
-                                      "speedup": t_per_mock / t_batched, "counts_identical": same}
-        # the small workload, where launch overhead dominates
-        c1 = mockgen.make_catalogues(mockgen.WORKLOADS["c1"])
-        p1 = Pipeline(c1)
-        p1.build_cells()
-        p1.count()
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(5):
-            t0 = time.perf_counter()
-            p1.count()
+        # Batched (one persistent launch), the same launch replayed from a
+        # captured hipGraph, and the per-mock baseline (one launch per task,
+        # mock after mock, a synchronisation after each mock), each run once
+        # untimed and then timed as the median of a few wall-clock runs.
+        def wall(fn, reps):
+            ts = []
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return float(np.median(ts)), ts
+
+        def compare(p, reps):
+            p.count()
             torch.cuda.synchronize()
-            ts.append(time.perf_counter() - t0)
-        tp = []
-        for _ in range(2):
-            t0 = time.perf_counter()
-            p1.count_per_mock()
+            ref = p.counts.clone()
+            p.count_per_mock()
+            p.count(lc.LC_GRAPH)
             torch.cuda.synchronize()
-            tp.append(time.perf_counter() - t0)
-        out["batched_vs_per_mock_c1"] = {"workload": "c1", "batched_s": float(np.median(ts)),
-                                         "per_mock_s": float(np.median(tp)),
-                                         "speedup": float(np.median(tp) / np.median(ts))}
+            tb, tbs = wall(p.count, reps)
+            tg, tgs = wall(lambda: p.count(lc.LC_GRAPH), reps)
+            same = bool(torch.equal(ref, p.counts))
+            tp, tps = wall(p.count_per_mock, reps)
+            same = same and bool(torch.equal(ref, p.counts))
+            return {"batched_s": tb, "graph_replay_s": tg, "per_mock_s": tp, "speedup": tp / tb,
+                    "speedup_graph": tp / tg, "runs": reps, "batched_runs_s": tbs, "graph_runs_s": tgs,
+                    "per_mock_runs_s": tps, "counts_identical": same}
+
+        log("[bench] batched vs per-mock (%s)" % wl.name)
+        out["batched_vs_per_mock"] = dict(workload=wl.name, **compare(pl, 3))
+        if args.config != "c1":
+            # the small workload, where launch overhead dominates
+            c1 = mockgen.make_catalogues(mockgen.WORKLOADS["c1"])
+            p1 = Pipeline(c1)
+            p1.build_cells()
+            log("[bench] batched vs per-mock (c1)")
+            out["batched_vs_per_mock_c1"] = dict(workload="c1", **compare(p1, 5))
+            del p1
 
     # predicted error of the covariance estimates at M = 50 (Sect. 3, 5.3)
     out["covcov_M50"] = pl.covcov(50.0)

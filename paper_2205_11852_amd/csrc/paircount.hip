@@ -721,39 +721,59 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                 }
                 // j points gathered into blocks of 64 (one per lane) across runs
                 // of kept sub-cells and stencil offsets
-                // Stage 1: gathered j points, one per lane in lanes [0, fill):
-                // coordinates in the i cell frame, j index relative to the chunk
-                // start for points of the i cell itself (auto pairs: count only
-                // j > i; INT_MAX otherwise; i indices within the chunk are below
-                // 256, so clamping large offsets keeps every comparison) and,
-                // for the midpoint line of sight, the byte offset of the point in
-                // its catalogue's absolute coordinates.
+                // the wave's share of the bound on every bin, and the count of
+                // candidate tests, before nfill j points meet the chunk
+                auto account = [&](int nfill) {
+                    const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
+                    w.n_cand += nc;
+                    // (nc <= 2^14; the sum is taken in 64 bits, so a limit of
+                    // 2^32 - 1 cannot wrap)
+                    if (uint64_t(w.since_flush) + nc >= uint64_t(p.wave_limit))
+                        wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
+                    w.since_flush += uint32_t(nc);
+                };
+                // Auto pairs inside the i cell (i < j): its points after the
+                // chunk start, in blocks of 64 swept directly by the block's
+                // first wave, each lane's j index relative to the chunk start
+                // (i indices within the chunk are below 256).
+                if (autop && wid == 0) {
+                    for (int64_t jb = ib + 1; jb < ia1; jb += 64) {
+                        const int n = int(min(ia1 - jb, int64_t(64)));
+                        const int32_t jo = int32_t(jb - w.b0);
+                        const int32_t io = int32_t(jb - ib);
+                        float x = -1e18f, y = -1e18f, z = -1e18f, wj = 0.0f;
+                        int rel = INT_MAX;
+                        if (lane < n) {
+                            const uint32_t off = uint32_t(lane + jo) * 12u;
+                            const float* q =
+                                reinterpret_cast<const float*>(reinterpret_cast<const char*>(w.pj) + off);
+                            x = q[0];
+                            y = q[1];
+                            z = q[2];
+                            rel = lane + io;
+                            if (LOS == 1) wj = __int_as_float(int(off));
+                        }
+                        account(n);
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, x, y, z, rel, wj, pts, ib, n_i, p, xt);
+                    }
+                }
+                // The other j points go through two stages.  Stage 1: gathered
+                // points, one per lane in lanes [0, fill): coordinates in the i
+                // cell frame and, for the midpoint line of sight, the byte
+                // offset of the point in its catalogue's absolute coordinates.
                 float sx = 0.0f, sy = 0.0f, sz = 0.0f, sw = 0.0f;
-                int srel = INT_MAX;
                 int fill = 0;
                 // Stage 2: the kept points, lanes [0, kfill): the block that is
                 // swept against the chunk.
                 float kx = -1e18f, ky = -1e18f, kz = -1e18f, kw = 0.0f;
-                int krel = INT_MAX;
                 int kfill = 0;
                 auto process = [&](int nfill) {
                     const bool vj = lane < nfill;
                     // lanes past nfill hold a point far from every i point
                     const float xj = vj ? kx : -1e18f, yj = vj ? ky : -1e18f, zj = vj ? kz : -1e18f;
-                    const int jrel = vj ? krel : INT_MAX;
-                    const uint64_t nc = uint64_t(n_i) * uint64_t(nfill);
-                    w.n_cand += nc;
-                    // keep this wave's share of the bound on every bin (nc <= 2^14;
-                    // the sum is taken in 64 bits, so a limit of 2^32 - 1 cannot wrap)
-                    if (uint64_t(w.since_flush) + nc >= uint64_t(p.wave_limit))
-                        wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
-                    w.since_flush += uint32_t(nc);
-                    if (__builtin_amdgcn_ballot_w64(jrel != INT_MAX))
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, xj, yj, zj, jrel, kw, pts, ib, n_i, p,
-                                                                  xt);
-                    else
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, jrel, kw, pts, ib, n_i, p,
-                                                                   xt);
+                    account(nfill);
+                    sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, INT_MAX, kw, pts, ib, n_i, p,
+                                                               xt);
                 };
                 // Move the stage-1 points that lie within r_max of the chunk's
                 // box into lanes [kfill, ...) of the kept block (one cross-lane
@@ -788,14 +808,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     const float px = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sx)));
                     const float py = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sy)));
                     const float pz = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sz)));
-                    const int prel = __builtin_amdgcn_ds_permute(to, srel);
                     const float pw =
                         LOS == 1 ? __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sw))) : 0.0f;
                     const bool take = lane >= kfill;
                     kx = take ? px : kx;
                     ky = take ? py : ky;
                     kz = take ? pz : kz;
-                    krel = take ? prel : krel;
                     if (LOS == 1) kw = take ? pw : kw;
                     const int end = kfill + int(nk);
                     if (end < 64) {
@@ -806,7 +824,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     sx = px;
                     sy = py;
                     sz = pz;
-                    srel = prel;
                     if (LOS == 1) sw = pw;
                     fill = end - 64;
                     kfill = 64;
@@ -814,6 +831,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                 };
                 // the block's waves share the stencil offsets of the chunk
                 for (int s = wid; s < ns; s += nwave) {
+                    if (autop && s == 0) continue;  // the i cell itself: above
                     const int4 o = sten[s];
                     int jx = cx + o.x, jy = cy + o.y, jz = cz + o.z;
                     int shx = 0, shy = 0, shz = 0;
@@ -830,14 +848,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     const float dox = float(ox[jx] + shx - oix);
                     const float doy = float(oy[jy] + shy - oiy);
                     const float doz = float(oz[jz] + shz - oiz);
-                    const bool self = autop && s == 0;
+                    // sub-cells farther than r_max from the chunk's box hold no
+                    // binned pair; their box is widened by 2 units for the
+                    // rounding of the integer cell boundaries
                     unsigned long long runs;
-                    if (self) {
-                        runs = 0;  // i < j inside the i cell: one range, below
-                    } else {
-                        // sub-cells farther than r_max from the chunk's box hold no
-                        // binned pair; their box is widened by 2 units for the
-                        // rounding of the integer cell boundaries
+                    {
                         const float lx = dox + float(slx) * p.wf[0] - 2.0f, hx = lx + p.wf[0] + 4.0f;
                         const float ly = doy + float(sly) * p.wf[1] - 2.0f, hy = ly + p.wf[1] + 4.0f;
                         const float lz = doz + float(slz) * p.wf[2] - 2.0f, hz = lz + p.wf[2] + 4.0f;
@@ -854,30 +869,19 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         }
                         runs = __builtin_amdgcn_ballot_w64((lane < nsub) && keep);
                     }
-                    while (self || runs) {
-                        int64_t jb, je;
-                        if (self) {
-                            jb = ib + 1;
-                            je = ia1;
-                        } else {
-                            // next run of consecutive kept sub-cells = one range of points
-                            const int s0 = __builtin_ctzll(runs);
-                            const unsigned long long rest = ~(runs >> s0);
-                            const int e = rest ? s0 + __builtin_ctzll(rest) : 64;
-                            jb = cs[sbase + s0];
-                            je = cs[sbase + e];
-                            runs = (e >= 64) ? 0ull : (runs & (~0ull << e));
-                        }
-                        jb = uniform64(jb);
-                        je = uniform64(je);
+                    while (runs) {
+                        // next run of consecutive kept sub-cells = one range of points
+                        const int s0 = __builtin_ctzll(runs);
+                        const unsigned long long rest = ~(runs >> s0);
+                        const int e = rest ? s0 + __builtin_ctzll(rest) : 64;
+                        int64_t jb = uniform64(cs[sbase + s0]);
+                        const int64_t je = uniform64(cs[sbase + e]);
+                        runs = (e >= 64) ? 0ull : (runs & (~0ull << e));
                         while (jb < je) {
-                            // lanes [fill, fill + take) take points jb, jb + 1, ...
+                            // lanes [fill, fill + take) take points jb, jb + 1, ...,
+                            // each by its byte offset in the j catalogue
                             const int take = int(min(je - jb, int64_t(64 - fill)));
-                            // lane's point: jb + lane - fill, as a byte offset in the
-                            // j catalogue (and, for the i cell itself, as an index
-                            // relative to the chunk start: both below 2^31)
                             const int32_t jo = int32_t(jb - w.b0) - fill;
-                            const int32_t io = self ? int32_t(jb - ib) - fill : 0;
                             if (lane >= fill && lane < fill + take) {
                                 const uint32_t off = uint32_t(lane + jo) * 12u;
                                 const float* q = reinterpret_cast<const float*>(
@@ -885,7 +889,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                                 sx = q[0] + dox;
                                 sy = q[1] + doy;
                                 sz = q[2] + doz;
-                                srel = self ? lane + io : INT_MAX;
                                 if (LOS == 1) sw = __int_as_float(int(off));
                             }
                             fill += take;
@@ -895,7 +898,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                                 kfill = 0;
                             }
                         }
-                        if (self) break;
                     }
                 }
                 // the rest of stage 1 (a full kept block leaves fewer than 64
