@@ -172,6 +172,13 @@ typedef struct {
                                  tasks; LC_QUEUE_XCD_DEALT: the cost order dealt to the eight
                                  XCD queues in turn; LC_QUEUE_SHARED: one queue for every block.
                                  A block whose queue is empty takes work from the next one */
+    int32_t hist_bits;        /* block histogram bins: 0 = library choice (32-bit, or two 16-bit
+                                 bins per word where the 32-bit histogram keeps waves off the CU,
+                                 as with 200 x 100 bins), 16 or 32.  A 16-bit bin that wraps is
+                                 corrected in the counts at once, so counts stay exact */
+    int32_t wrap_test;        /* testing: with 16-bit bins, every bin starts 16 counts below its
+                                 wrap (the start values are taken off again), so the wrap
+                                 corrections run all the time */
 } lc_tuning;
 
 #define LC_QUEUE_XCD_RANGES 0

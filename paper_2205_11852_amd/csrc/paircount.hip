@@ -45,6 +45,8 @@ namespace lc {
 constexpr int kQ = 128;     // entries of the per-wave compaction queue
 static_assert(kQ >= 127, "a drain reads queue slots up to 63 + 63");
 constexpr int kX = 128;     // entries of the per-wave queue of pairs for the integer rule
+constexpr int kX16 = 64;    // the same with 16-bit bins (less LDS per wave, more waves per CU)
+constexpr int kx_for(bool h16) { return h16 ? kX16 : kX; }
 constexpr int kXcd = 8;     // queues (one per XCD)
 
 struct PcParams {
@@ -62,7 +64,7 @@ struct PcParams {
     int32_t cells_per_item, items_per_task;
     int32_t chunk, pad3;        // i points per chunk (multiple of 4, <= 64)
     int32_t n_r, n_mu, nbins;
-    int32_t hist_stride;    // uint32 words per wave histogram (bins + a discard slot)
+    int32_t hist_stride;    // uint32 words of the block histogram (bins + a discard slot)
     int32_t queue_byte0;    // LDS byte offset of wave 0's queue
     int32_t pad2;
     float emax2_hi, emin2_lo;   // phase A acceptance (float32, with margin)
@@ -71,7 +73,8 @@ struct PcParams {
     // on their fractions (see bin_fast)
     float r_shift, ok_r, mu_shift, ok_m;
     float pimax_f;              // (r_p, pi) binning: |s_z| bound (an exact integer)
-    uint32_t nmu4;              // 4 n_mu: bytes per r row of the histogram
+    uint32_t nmu4;              // bytes per r row of the histogram: 4 n_mu (2 n_mu with 16-bit bins)
+    uint32_t h16_init;          // 16-bit bins: initial value of a histogram word (two bins)
     uint32_t wave_limit;        // candidate tests a wave may register between flushes
     uint32_t qstart[kXcd + 1];  // queue x holds items [qstart[x], qstart[x+1])
 };
@@ -240,6 +243,8 @@ struct BinConst {
 
 struct WaveState {
     BinConst bc;
+    unsigned long long* dst;  // 16-bit bins: the current task's counts (wrap corrections)
+    int32_t nbins;            // 16-bit bins: bins of a task (slots past it are the discard slot)
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
@@ -280,7 +285,7 @@ __device__ __forceinline__ void wave_sync_lds() {
 // integer rule later.  d2 = 0 (and q = 0) give NaN or clamped estimates that
 // fail the test, so every value stays finite.  (A bound below 0 sends every
 // pair to the integer rule.)
-template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL, bool H16>
 __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
                                              const PcParams& p, const BinConst& bc, float& fm, float& fr) {
     // Each estimate is shifted down by its margin eps inside the FMA that
@@ -334,7 +339,7 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         fr = __builtin_amdgcn_fractf(t);
     }
     // 24-bit multiply-add: k < n_r and 4 n_mu are far below 2^24
-    return __umul24(k, LOS == 1 ? bc.nmu4 : p.nmu4) + (m << 2);
+    return __umul24(k, LOS == 1 ? bc.nmu4 : p.nmu4) + (m << (H16 ? 1 : 2));
 }
 
 // Histogram slot of one queued pair by the integer rule (discard slot when it
@@ -368,16 +373,52 @@ __device__ __forceinline__ int exact_entry(const float4 e, const float* __restri
                                    uint64_t(Q), k_est, m_est, xt);
 }
 
+// A 16-bit bin wrapped from 65535 to 0: add its lost 65536 to the task's
+// counts.  Bins 2t (low half) and 2t + 1 (high half) share LDS word t, so a
+// wrap of the low half also carried one into the high half, whose count then
+// loses it again; and if that carry wrapped the high half, the high bin lost
+// 65536 too.  Every wrap is seen by exactly the atomic add that caused it (it
+// returns the word's old value), so the corrections are exact whatever the
+// order of the adds; the uint64 counts take -1 as 2^64 - 1.
+__device__ __noinline__ void h16_wrap(const WaveState& w, uint32_t slot, uint32_t sh, uint32_t old) {
+    const uint32_t lo = slot & ~1u, hi = lo + 1;
+    unsigned long long* d = w.dst;
+    const uint32_t nb = uint32_t(w.nbins);
+    if (sh == 0) {
+        if (lo < nb) __hip_atomic_fetch_add(d + lo, 65536ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (hi < nb) {
+            const unsigned long long c = (old >> 16) == 0xFFFFu ? 65535ull : ~0ull;
+            __hip_atomic_fetch_add(d + hi, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else if (hi < nb) {
+        __hip_atomic_fetch_add(d + hi, 65536ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Add one to the histogram slot at LDS byte address `addr` (the histogram
+// starts at address 0): a 32-bit bin, or with H16 a 16-bit half of a word.
+template <bool H16>
+__device__ __forceinline__ void hist_add(const WaveState& w, uint32_t addr) {
+    if (!H16) {
+        __hip_atomic_fetch_add(lds_u32_at(addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+        const uint32_t sh = (addr & 2u) << 3;
+        const uint32_t old =
+            __hip_atomic_fetch_add(lds_u32_at(addr & ~3u), 1u << sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (((old >> sh) & 0xFFFFu) == 0xFFFFu) h16_wrap(w, addr >> 1, sh, old);
+    }
+}
+
 // Bin the last n (<= 64) of the xn pairs waiting for the integer rule, one
 // per lane with every lane busy.  Returns the new length.
-template <int LOS, bool UNIFORM>
+template <int LOS, bool UNIFORM, bool H16>
 __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t n, uint32_t xn,
                                                 const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = xn - n;
     if (uint32_t(lane) < n) {
         const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], w.ai, w.ai_last, xt);
-        __hip_atomic_fetch_add(&w.hist[bin], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        hist_add<H16>(w, uint32_t(bin) << (H16 ? 1 : 2));
         w.n_exact++;
     }
     wave_sync_lds();
@@ -392,14 +433,14 @@ __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t
 // entries in, since the queue held fewer than 64 before the last append of
 // at most 64; a partial drain starts at 0), and lanes past n are masked.
 // FULL: n = 64, so every slot read holds an entry of the current task.
-template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL, bool H16>
 __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, uint32_t qt, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
     wave_sync_lds();
     const uint32_t first = qt - n;
     const float4 e = w.qa[first + lane];
     float fm, fr;
-    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0, FULL>(e, w.ai, w.ai_last, p, w.bc, fm, fr);
+    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0, FULL, H16>(e, w.ai, w.ai_last, p, w.bc, fm, fr);
     const float ok_m = LOS == 1 ? w.bc.ok_m : p.ok_m;
     const bool live = uint32_t(lane) < n;
     const unsigned long long live_mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
@@ -411,17 +452,19 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
     const unsigned long long xb =
         live_mask & ~(__builtin_amdgcn_fcmpf(fm, ok_m, 4) & __builtin_amdgcn_fcmpf(fr, p.ok_r, 4));
     const bool ok = (fm < ok_m) && (fr < p.ok_r);
-    if (ok && live)
-        __hip_atomic_fetch_add(lds_u32_at(addr), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (ok && live) hist_add<H16>(w, addr);
     if (xb) {
         uint32_t xn = __builtin_amdgcn_readfirstlane(w.xn);
+        // H16 (a queue of kX16): a queue that would pass it is binned first
+        if (H16 && xn + uint32_t(__popcll(xb)) > uint32_t(kX16))
+            xn = drain_exact<LOS, UNIFORM, H16>(w, lane, xn, xn, xt);
         if (live && !ok) {
             const uint32_t rank =
                 __builtin_amdgcn_mbcnt_hi(uint32_t(xb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(xb), 0u));
             w.xa[xn + rank] = e;
         }
         xn = __builtin_amdgcn_readfirstlane(xn + uint32_t(__popcll(xb)));
-        if (xn >= 64) xn = drain_exact<LOS, UNIFORM>(w, lane, 64, xn, xt);
+        if (xn >= 64) xn = drain_exact<LOS, UNIFORM, H16>(w, lane, 64, xn, xt);
         w.xn = xn;
     }
     wave_sync_lds();
@@ -429,11 +472,23 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
 }
 
 // Bin everything this wave has queued (both queues).
-template <int LOS, bool UNIFORM, bool HAS_E0>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool H16>
 __device__ __forceinline__ void drain_all(WaveState& w, int lane, const PcParams& p,
                                           const ExactTab* __restrict__ xt) {
-    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0, false>(w, lane, w.qtail, w.qtail, p, xt);
-    if (w.xn) w.xn = drain_exact<LOS, UNIFORM>(w, lane, w.xn, w.xn, xt);
+    if (w.qtail) w.qtail = drain<LOS, UNIFORM, HAS_E0, false, H16>(w, lane, w.qtail, w.qtail, p, xt);
+    if (w.xn) w.xn = drain_exact<LOS, UNIFORM, H16>(w, lane, w.xn, w.xn, xt);
+}
+
+// Add the two 16-bit bins of histogram word t (slots 2t, 2t + 1) to the
+// task's counts, less the value each bin started from (h16_init's halves;
+// nonzero only in the wrap test mode), modulo 2^64.
+__device__ __forceinline__ void h16_flush_word(uint32_t v, uint32_t init, int t, int nbins,
+                                               unsigned long long* __restrict__ dst) {
+    const unsigned long long lo = (v & 0xFFFFu), lo0 = (init & 0xFFFFu);
+    const unsigned long long hi = (v >> 16), hi0 = (init >> 16);
+    if (lo != lo0) __hip_atomic_fetch_add(dst + 2 * t, lo - lo0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hi != hi0 && 2 * t + 1 < nbins)
+        __hip_atomic_fetch_add(dst + 2 * t + 1, hi - hi0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Every bin value is at most the sum over the block's waves of the candidate
@@ -442,14 +497,24 @@ __device__ __forceinline__ void drain_all(WaveState& w, int lane, const PcParams
 // pass that bound bins its queue and then moves the whole histogram out with
 // atomic exchanges: counts other waves add meanwhile stay in the bins, and
 // their shares still cover them.
-template <int LOS, bool UNIFORM, bool HAS_E0>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool H16>
 __device__ __forceinline__ void wave_flush(WaveState& w, int lane, const PcParams& p,
                                            const ExactTab* __restrict__ xt,
                                            unsigned long long* __restrict__ dst) {
-    drain_all<LOS, UNIFORM, HAS_E0>(w, lane, p, xt);
-    for (int b = lane; b < p.nbins; b += 64) {
-        const unsigned v = __hip_atomic_exchange(&w.hist[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (v) __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    drain_all<LOS, UNIFORM, HAS_E0, H16>(w, lane, p, xt);
+    if (!H16) {
+        for (int b = lane; b < p.nbins; b += 64) {
+            const unsigned v = __hip_atomic_exchange(&w.hist[b], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (v) __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    } else {
+        // both halves of every word move out together; a half that wraps
+        // meanwhile is corrected by its own add (h16_wrap)
+        for (int t = lane; 2 * t < p.nbins; t += 64) {
+            const unsigned v =
+                __hip_atomic_exchange(&w.hist[t], p.h16_init, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            h16_flush_word(v, p.h16_init, t, p.nbins, dst);
+        }
     }
     w.since_flush = 0;
     w.n_wflush++;
@@ -457,13 +522,25 @@ __device__ __forceinline__ void wave_flush(WaveState& w, int lane, const PcParam
 
 // End of a task: every wave has binned its queue; the block adds the
 // histogram into the task's counts and clears it.  Called by all threads.
-__device__ __forceinline__ void block_flush(unsigned* hist, int nbins, unsigned long long* __restrict__ dst) {
+template <bool H16>
+__device__ __forceinline__ void block_flush(unsigned* hist, int nbins, uint32_t h16_init,
+                                            unsigned long long* __restrict__ dst) {
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-        const unsigned v = hist[b];
-        if (v) {
-            __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            hist[b] = 0;
+    if (!H16) {
+        for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+            const unsigned v = hist[b];
+            if (v) {
+                __hip_atomic_fetch_add(dst + b, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                hist[b] = 0;
+            }
+        }
+    } else {
+        for (int t = threadIdx.x; 2 * t < nbins; t += blockDim.x) {
+            const unsigned v = hist[t];
+            if (v != h16_init) {
+                h16_flush_word(v, h16_init, t, nbins, dst);
+                hist[t] = h16_init;
+            }
         }
     }
     __syncthreads();
@@ -501,7 +578,7 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
 // wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the j point's
 // byte offset in the task's j catalogue (midpoint); the other modes queue d2
 // (r_p^2).
-template <int LOS, bool UNIFORM, bool HAS_E0>
+template <int LOS, bool UNIFORM, bool HAS_E0, bool H16>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
                                          uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
     qt = __builtin_amdgcn_readfirstlane(qt);
@@ -516,7 +593,7 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
                 make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
-        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0, true>(w, lane, 64, qt, p, xt);
+        if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0, true, H16>(w, lane, 64, qt, p, xt);
     }
     return qt;
 }
@@ -526,7 +603,7 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
 // the four lie past the chunk (still inside the padded point array); their
 // tests are computed and their ballots cleared.  jw: this lane's j point as
 // queued for the midpoint line of sight (its byte offset, as float bits).
-template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL>
+template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL, bool H16>
 __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
                                                 int jrel, const float* __restrict__ q, float jw, int k,
                                                 int n_i, uint32_t qt, const PcParams& p,
@@ -555,14 +632,14 @@ __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj
     }
 #pragma unroll
     for (int u = 0; u < 4; u++)
-        qt = push<LOS, UNIFORM, HAS_EMIN>(w, lane, c[u], jw, bal[u], qt, p, xt);
+        qt = push<LOS, UNIFORM, HAS_EMIN, H16>(w, lane, c[u], jw, bal[u], qt, p, xt);
     return qt;
 }
 
 // Test the n_i points of the i chunk (ib .. ib + n_i - 1) against the j block.
 // The chunk's 768 bytes stay in the scalar cache while every j block of the
 // chunk sweeps them.
-template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF>
+template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool H16>
 __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int jrel,
                                             float jw, const float* __restrict__ pts, int64_t ib, int n_i,
                                             const PcParams& p, const ExactTab* __restrict__ xt) {
@@ -570,17 +647,17 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
     uint32_t qt = w.qtail;
     int k = 0;
     for (; k + 4 <= n_i; k += 4)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false, H16>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
                                                               k, n_i, qt, p, xt);
     if (k < n_i)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true, H16>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
                                                              k, n_i, qt, p, xt);
     w.qtail = qt;
 }
 
 // Six waves per SIMD (80 VGPRs): latency hiding pays more than the few
 // registers this spills outside the inner loops.
-template <int LOS, bool UNIFORM, bool HAS_EMIN>
+template <int LOS, bool UNIFORM, bool HAS_EMIN, bool H16>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
     const float* __restrict__ pts, const float* __restrict__ apts, const int64_t* __restrict__ cs,
     const int2* __restrict__ tasks, const int32_t* __restrict__ order, const int4* __restrict__ sten,
@@ -611,13 +688,17 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     } else {
         w.qbyte = qbyte;
     }
-    w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kX;
+    w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kx_for(H16);
     w.xn = 0;
     w.qtail = 0;
     w.since_flush = 0;
     w.n_cand = 0;
     w.n_exact = w.n_flush = w.n_wflush = 0;
-    for (int b = threadIdx.x; b < p.hist_stride; b += blockDim.x) w.hist[b] = 0;
+    for (int b = threadIdx.x; b < p.hist_stride; b += blockDim.x) w.hist[b] = H16 ? p.h16_init : 0u;
+    if (H16) {
+        w.nbins = p.nbins;
+        w.dst = counts;
+    }
 
     // work items are taken by the whole block (thread 0 pops, the others read
     // the item from LDS), so the block's waves always count the same task
@@ -653,12 +734,13 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
         task = __builtin_amdgcn_readfirstlane(task);
         if (task != cur_task) {
             if (cur_task >= 0) {
-                drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
-                block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
+                drain_all<LOS, UNIFORM, HAS_EMIN, H16>(w, lane, p, xt);
+                block_flush<H16>(w.hist, p.nbins, p.h16_init, counts + int64_t(cur_task) * p.nbins);
                 if (threadIdx.x == 0) w.n_flush++;
             }
             w.since_flush = 0;
             cur_task = task;
+            if (H16) w.dst = counts + int64_t(task) * p.nbins;
             // the task's j catalogue: points are gathered by their byte
             // offset from its first point (catalogues hold fewer than 2^28
             // points); midpoint entries queued from here on hold such
@@ -729,7 +811,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     // (nc <= 2^14; the sum is taken in 64 bits, so a limit of
                     // 2^32 - 1 cannot wrap)
                     if (uint64_t(w.since_flush) + nc >= uint64_t(p.wave_limit))
-                        wave_flush<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt, dst);
+                        wave_flush<LOS, UNIFORM, HAS_EMIN, H16>(w, lane, p, xt, dst);
                     w.since_flush += uint32_t(nc);
                 };
                 // Auto pairs inside the i cell (i < j): its points after the
@@ -754,7 +836,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                             if (LOS == 1) wj = __int_as_float(int(off));
                         }
                         account(n);
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true>(w, lane, x, y, z, rel, wj, pts, ib, n_i, p, xt);
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true, H16>(w, lane, x, y, z, rel, wj, pts, ib, n_i, p, xt);
                     }
                 }
                 // The other j points go through two stages.  Stage 1: gathered
@@ -772,7 +854,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     // lanes past nfill hold a point far from every i point
                     const float xj = vj ? kx : -1e18f, yj = vj ? ky : -1e18f, zj = vj ? kz : -1e18f;
                     account(nfill);
-                    sweep_block<LOS, UNIFORM, HAS_EMIN, false>(w, lane, xj, yj, zj, INT_MAX, kw, pts, ib, n_i, p,
+                    sweep_block<LOS, UNIFORM, HAS_EMIN, false, H16>(w, lane, xj, yj, zj, INT_MAX, kw, pts, ib, n_i, p,
                                                                xt);
                 };
                 // Move the stage-1 points that lie within r_max of the chunk's
@@ -913,8 +995,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
         }
     }
     if (cur_task >= 0) {
-        drain_all<LOS, UNIFORM, HAS_EMIN>(w, lane, p, xt);
-        block_flush(w.hist, p.nbins, counts + int64_t(cur_task) * p.nbins);
+        drain_all<LOS, UNIFORM, HAS_EMIN, H16>(w, lane, p, xt);
+        block_flush<H16>(w.hist, p.nbins, p.h16_init, counts + int64_t(cur_task) * p.nbins);
         if (threadIdx.x == 0) w.n_flush++;
     }
     if (stats) {
@@ -931,16 +1013,22 @@ typedef void (*PcKernel)(const float*, const float*, const int64_t*, const int2*
                          const ExactTab*, const int32_t*, unsigned long long*, unsigned long long*, unsigned*,
                          PcParams);
 
-static PcKernel pick_kernel(int los, bool uniform, bool has_emin) {
-    static const PcKernel tab[3][2][2] = {
-        {{k_pair_count<0, false, false>, k_pair_count<0, false, true>},
-         {k_pair_count<0, true, false>, k_pair_count<0, true, true>}},
-        {{k_pair_count<1, false, false>, k_pair_count<1, false, true>},
-         {k_pair_count<1, true, false>, k_pair_count<1, true, true>}},
-        {{k_pair_count<2, false, false>, k_pair_count<2, false, true>},
-         {k_pair_count<2, true, false>, k_pair_count<2, true, true>}},
+static PcKernel pick_kernel(int los, bool uniform, bool has_emin, bool h16) {
+    static const PcKernel tab[2][3][2][2] = {
+        {{{k_pair_count<0, false, false, false>, k_pair_count<0, false, true, false>},
+          {k_pair_count<0, true, false, false>, k_pair_count<0, true, true, false>}},
+         {{k_pair_count<1, false, false, false>, k_pair_count<1, false, true, false>},
+          {k_pair_count<1, true, false, false>, k_pair_count<1, true, true, false>}},
+         {{k_pair_count<2, false, false, false>, k_pair_count<2, false, true, false>},
+          {k_pair_count<2, true, false, false>, k_pair_count<2, true, true, false>}}},
+        {{{k_pair_count<0, false, false, true>, k_pair_count<0, false, true, true>},
+          {k_pair_count<0, true, false, true>, k_pair_count<0, true, true, true>}},
+         {{k_pair_count<1, false, false, true>, k_pair_count<1, false, true, true>},
+          {k_pair_count<1, true, false, true>, k_pair_count<1, true, true, true>}},
+         {{k_pair_count<2, false, false, true>, k_pair_count<2, false, true, true>},
+          {k_pair_count<2, true, false, true>, k_pair_count<2, true, true, true>}}},
     };
-    return tab[los][uniform ? 1 : 0][has_emin ? 1 : 0];
+    return tab[h16 ? 1 : 0][los][uniform ? 1 : 0][has_emin ? 1 : 0];
 }
 
 __global__ void k_zero_counters(unsigned* q, int n) {
@@ -1023,8 +1111,6 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     p.n_r = n_r;
     p.n_mu = n_mu;
     p.nbins = n_r * n_mu;
-    p.nmu4 = uint32_t(4 * n_mu);
-    p.hist_stride = (p.nbins + 1 + 3) & ~3;  // + the discard slot
     const bool mid = b->los == LC_LOS_MID;
     const int max_chunk = 256;
     // default: a whole cell per gather of its j points (fewer, larger chunks
@@ -1033,7 +1119,6 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     if (chunk > max_chunk || chunk % 4 != 0)
         return fail(LC_ERR_INVALID, "chunk = %d, must be a multiple of 4 in [4, %d]", chunk, max_chunk);
     p.chunk = chunk;
-    p.queue_byte0 = (p.hist_stride * 4 + 16 + 15) & ~15;
     const int64_t e0 = b->r_edges[0];
     const int64_t de = int64_t(b->r_edges[1]) - b->r_edges[0];
     bool uniform = true;
@@ -1083,68 +1168,116 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
     // takes the integer rule
     if (mode & LC_FORCE_EXACT) p.ok_r = -1.0f;
     const bool has_emin = e0 > 0;
-    pl.kern = pick_kernel(mid ? 1 : rppi ? 2 : 0, uniform, has_emin);
-    {
-        // the histogram is addressed from LDS address 0 (lds_u32_at): the
-        // dynamic block must not follow any static LDS
-        hipFuncAttributes fa;
-        LC_TRY_HIP(hipFuncGetAttributes(&fa, (const void*)pl.kern));
-        if (fa.sharedSizeBytes != 0)
-            return fail(LC_ERR_HIP, "pair-count kernel holds %zu bytes of static LDS", size_t(fa.sharedSizeBytes));
-    }
     pl.mode = mode;
     pl.n_tasks = n_tasks;
-
-    auto lds_for = [&](int w) { return size_t(p.queue_byte0) + size_t(w) * (kQ + kX) * 16; };
-    if (lds_for(1) > ctx->max_lds_block)
-        return fail(LC_ERR_INVALID, "histogram of %d bins does not fit in LDS", p.nbins);
-    if (lds_for(16) > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void*)pl.kern, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(std::min(lds_for(16), ctx->max_lds_block)));
-        if (e != hipSuccess) return fail(LC_ERR_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
-    }
-    int wpb = 0, occ = 0;
-    if (tune && tune->waves_per_block > 0) {
-        wpb = tune->waves_per_block;
-        if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 16)
-            return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4, 8 or 16", wpb);
-        while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
-        LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
-    } else if (mode & LC_PER_TASK) {
-        // one task per launch has few items: the largest blocks finish each
-        // item soonest, which shortens the launch's tail (1000 c2 mocks: 2.85 s
-        // with 16 waves per block against 4.30 s with 4)
-        wpb = 16;
-        while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
-        LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
-    } else {
-        // the block shape that keeps the most waves resident per CU, the
-        // smallest on a tie: a small histogram leaves room for several
-        // 4-wave blocks, a large one for a single block, which then holds
-        // more waves sharing its histogram
-        int best = -1;
-        for (int w : {4, 8, 16}) {
-            if (lds_for(w) > ctx->max_lds_block) continue;
-            int o = 0;
-            LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void*)pl.kern, w * 64, lds_for(w)));
-            if (o * w > best) {
-                best = o * w;
-                wpb = w;
-                occ = o;
+    // Histogram layout: 32-bit bins, or two 16-bit bins per word (H16) with
+    // exact wrap accounting and a shorter integer-rule queue: half the LDS
+    // for a large histogram, so more waves fit on a CU.
+    const int los_k = mid ? 1 : rppi ? 2 : 0;
+    const int hist_bits = tune ? tune->hist_bits : 0;
+    if (hist_bits != 0 && hist_bits != 16 && hist_bits != 32)
+        return fail(LC_ERR_INVALID, "hist_bits = %d, must be 0, 16 or 32", hist_bits);
+    struct Shape {
+        bool h16;
+        PcKernel kern;
+        int32_t hist_stride, queue_byte0;
+        int wpb, occ;
+    };
+    auto lds_of = [&](const Shape& sh, int w) {
+        return size_t(sh.queue_byte0) + size_t(w) * (kQ + kx_for(sh.h16)) * 16;
+    };
+    auto shape_for = [&](bool h16, Shape& sh) -> lc_status {
+        sh.h16 = h16;
+        sh.kern = pick_kernel(los_k, uniform, has_emin, h16);
+        // + the discard slot
+        sh.hist_stride = h16 ? ((p.nbins + 1 + 1) / 2 + 3) & ~3 : (p.nbins + 1 + 3) & ~3;
+        sh.queue_byte0 = (sh.hist_stride * 4 + 16 + 15) & ~15;
+        sh.wpb = sh.occ = 0;
+        {
+            // the histogram is addressed from LDS address 0 (lds_u32_at): the
+            // dynamic block must not follow any static LDS
+            hipFuncAttributes fa;
+            LC_TRY_HIP(hipFuncGetAttributes(&fa, (const void*)sh.kern));
+            if (fa.sharedSizeBytes != 0)
+                return fail(LC_ERR_HIP, "pair-count kernel holds %zu bytes of static LDS",
+                            size_t(fa.sharedSizeBytes));
+        }
+        if (lds_of(sh, 1) > ctx->max_lds_block)
+            return fail(LC_ERR_INVALID, "histogram of %d bins does not fit in LDS", p.nbins);
+        if (lds_of(sh, 16) > 65536) {
+            hipError_t e = hipFuncSetAttribute((const void*)sh.kern, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                               int(std::min(lds_of(sh, 16), ctx->max_lds_block)));
+            if (e != hipSuccess) return fail(LC_ERR_HIP, "hipFuncSetAttribute: %s", hipGetErrorString(e));
+        }
+        int& wpb = sh.wpb;
+        int& occ = sh.occ;
+        if (tune && tune->waves_per_block > 0) {
+            wpb = tune->waves_per_block;
+            if (wpb != 1 && wpb != 2 && wpb != 4 && wpb != 8 && wpb != 12 && wpb != 16)
+                return fail(LC_ERR_INVALID, "waves_per_block = %d, must be 1, 2, 4, 8, 12 or 16", wpb);
+            while (wpb > 1 && lds_of(sh, wpb) > ctx->max_lds_block) wpb >>= 1;
+            LC_TRY_HIP(
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)sh.kern, wpb * 64, lds_of(sh, wpb)));
+        } else if (mode & LC_PER_TASK) {
+            // one task per launch has few items: the largest blocks finish each
+            // item soonest, which shortens the launch's tail (1000 c2 mocks: 2.85 s
+            // with 16 waves per block against 4.30 s with 4)
+            wpb = 16;
+            while (wpb > 1 && lds_of(sh, wpb) > ctx->max_lds_block) wpb >>= 1;
+            LC_TRY_HIP(
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)sh.kern, wpb * 64, lds_of(sh, wpb)));
+        } else {
+            // the block shape that keeps the most waves resident per CU, the
+            // smallest on a tie: a small histogram leaves room for several
+            // 4-wave blocks, a large one for a single block, which then holds
+            // more waves sharing its histogram (12-wave blocks with 16-bit
+            // bins: two of them fit where one 16-wave block did)
+            int best = -1;
+            for (int w : {4, 8, 12, 16}) {
+                if (w == 12 && !h16) continue;
+                if (lds_of(sh, w) > ctx->max_lds_block) continue;
+                int o = 0;
+                LC_TRY_HIP(
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, (const void*)sh.kern, w * 64, lds_of(sh, w)));
+                if (o * w > best) {
+                    best = o * w;
+                    wpb = w;
+                    occ = o;
+                }
+            }
+            if (wpb == 0) {
+                wpb = 4;
+                while (wpb > 1 && lds_of(sh, wpb) > ctx->max_lds_block) wpb >>= 1;
+                LC_TRY_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)sh.kern, wpb * 64,
+                                                                        lds_of(sh, wpb)));
             }
         }
-        if (wpb == 0) {
-            wpb = 4;
-            while (wpb > 1 && lds_for(wpb) > ctx->max_lds_block) wpb >>= 1;
-            LC_TRY_HIP(
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)pl.kern, wpb * 64, lds_for(wpb)));
-        }
+        return LC_OK;
+    };
+    Shape shape;
+    LC_TRY(shape_for(hist_bits == 16, shape));
+    if (hist_bits == 0 && !(mode & LC_PER_TASK)) {
+        // 16-bit bins only where the 32-bit histogram keeps waves off the CU
+        // (a 32-bit histogram costs nothing per pair; the 16-bit one costs
+        // the wrap check)
+        Shape s16;
+        LC_TRY(shape_for(true, s16));
+        if (s16.wpb * s16.occ > shape.wpb * shape.occ) shape = s16;
     }
+    const bool h16 = shape.h16;
+    pl.kern = shape.kern;
+    p.hist_stride = shape.hist_stride;
+    p.queue_byte0 = shape.queue_byte0;
+    p.nmu4 = uint32_t((h16 ? 2 : 4) * n_mu);
+    // wrap test: every 16-bit bin starts 16 counts below its wrap
+    p.h16_init = (h16 && tune && tune->wrap_test) ? 0xFFF0FFF0u : 0u;
+    int wpb = shape.wpb, occ = shape.occ;
     pl.threads = wpb * 64;
-    pl.lds = lds_for(wpb);
-    // each wave's share of the 2^32 bound on a histogram bin; a smaller
-    // flush_limit (testing) makes waves take the overflow guard early
-    p.wave_limit = uint32_t(0xFFFFFFFFu / unsigned(wpb));
+    pl.lds = lds_of(shape, wpb);
+    // each wave's share of the 2^32 bound on a 32-bit bin (16-bit bins are
+    // corrected at every wrap and need no bound); a smaller flush_limit
+    // (testing) makes waves take the overflow guard early
+    p.wave_limit = h16 ? 0xFFFFFFFFu : uint32_t(0xFFFFFFFFu / unsigned(wpb));
     if (tune && tune->flush_limit > 0) p.wave_limit = std::min(p.wave_limit, uint32_t(tune->flush_limit));
     occ = std::max(occ, 1);
     int bpc = tune && tune->blocks_per_cu > 0 ? std::min(tune->blocks_per_cu, occ) : occ;

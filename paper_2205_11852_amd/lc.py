@@ -60,7 +60,8 @@ class lc_task(ctypes.Structure):
 class lc_tuning(ctypes.Structure):
     _fields_ = [("cells_per_item", ctypes.c_int32), ("waves_per_block", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("flush_limit", ctypes.c_int32), ("queue_order", ctypes.c_int32)]
+                ("flush_limit", ctypes.c_int32), ("queue_order", ctypes.c_int32),
+                ("hist_bits", ctypes.c_int32), ("wrap_test", ctypes.c_int32)]
 
 
 class lc_mesh_opts(ctypes.Structure):
@@ -293,7 +294,8 @@ def _pair_count_args(cells, tasks, binning, counts, tune):
     if tune:
         tn = lc_tuning(int(tune.get("cells_per_item", 0)), int(tune.get("waves_per_block", 0)),
                        int(tune.get("blocks_per_cu", 0)), int(tune.get("chunk", 0)),
-                       int(tune.get("flush_limit", 0)), int(tune.get("queue_order", 0)))
+                       int(tune.get("flush_limit", 0)), int(tune.get("queue_order", 0)),
+                       int(tune.get("hist_bits", 0)), int(tune.get("wrap_test", 0)))
     return t, tn
 
 

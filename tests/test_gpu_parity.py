@@ -128,11 +128,15 @@ def test_c1_tunings_identical(c1, torch, tune):
     assert np.array_equal(pl.counts_host(), c1["ref"])
 
 
-def test_bad_queue_order_is_refused(c1, lcmod, torch):
+def test_bad_tuning_is_refused(c1, lcmod, torch):
     pl = c1["pl"]
     with pytest.raises(lcmod.LcError) as ei:
         pl.count(tune=dict(queue_order=3))
     assert ei.value.status == lcmod.LC_ERR_INVALID and "queue_order" in str(ei.value)
+    for bits in (8, 24, 64):
+        with pytest.raises(lcmod.LcError) as ei:
+            pl.count(tune=dict(hist_bits=bits))
+        assert ei.value.status == lcmod.LC_ERR_INVALID and "hist_bits" in str(ei.value)
 
 
 def test_c1_autotuned_counts_identical(c1, torch):
@@ -517,6 +521,56 @@ def test_overflow_guard_bit_exact(torch, lcmod, oracle_mod, case):
     assert pl.stats_host()["guard_flushes"] == 0
 
 
+@pytest.mark.parametrize("case", ["c1", "wedge", "rppi"])
+def test_sixteen_bit_bins_bit_exact(torch, lcmod, oracle_mod, case):
+    """The packed 16-bit histogram (two bins per LDS word, each wrap from
+    65535 to 0 corrected in the counts by the add that caused it), forced on
+    small workloads, with bins started 16 below their wrap (wrap_test) so
+    that wraps, carries from a low bin into its high neighbour and carries
+    that wrap the high bin happen all the time: counts bit-exact against the
+    oracle for 4-, 12- and 16-wave blocks, per-task launches and the
+    integer-rule-only mode."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    if case == "c1":
+        cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"], 6)
+        wl = cats.wl
+        edges, n_mu, box, los, pi_max = wl.r_edges_units, wl.n_mu, wl.box_units, "z", 0
+        bn = None
+    elif case == "wedge":
+        wl = dataclasses.replace(mockgen.WORKLOADS["c4"], n_mock=2, n_mean=6000.0, n_parents=300,
+                                 n_subsets=2, subset_size=6000)
+        cats = mockgen.make_catalogues(wl)
+        edges, n_mu, box, los, pi_max = wl.r_edges_units, wl.n_mu, 0, "mid", 0
+        bn = None
+    else:
+        cats = mockgen.make_catalogues(mockgen.WORKLOADS["c1"], 3)
+        box = cats.wl.box_units
+        edges = list(range(0, 13 * 5 * mockgen.UNITS_PER_MPC, 5 * mockgen.UNITS_PER_MPC))
+        n_mu, los, pi_max = 7, "rppi", 37 * mockgen.UNITS_PER_MPC
+        bn = lcmod.Binning(edges, n_mu, True, box, lcmod.LC_LOS_RPPI, pi_max)
+    pl = Pipeline(cats)
+    if bn is not None:
+        pl.binning = bn
+        pl.counts = torch.zeros((len(pl.tasks), bn.n_r, n_mu), dtype=torch.int64, device="cuda")
+    pl.build_cells()
+    refs = [oracle_mod.count_pairs(cats.cat(a), None if a == b else cats.cat(b), edges, n_mu, box, los,
+                                   pi_max=pi_max) for a, b in pl.tasks]
+    runs = [(lcmod.LC_PERSISTENT, dict(hist_bits=16)),
+            (lcmod.LC_PERSISTENT, dict(hist_bits=16, wrap_test=1)),
+            (lcmod.LC_PERSISTENT, dict(hist_bits=16, wrap_test=1, waves_per_block=12)),
+            (lcmod.LC_PERSISTENT, dict(hist_bits=16, wrap_test=1, waves_per_block=16, chunk=64)),
+            (lcmod.LC_PERSISTENT | lcmod.LC_FORCE_EXACT, dict(hist_bits=16, wrap_test=1)),
+            (lcmod.LC_PER_TASK, dict(hist_bits=16, wrap_test=1)),
+            (lcmod.LC_PERSISTENT, dict(hist_bits=16, wrap_test=1, flush_limit=2000))]
+    for mode, tune in runs:
+        _say("[h16]", case, "mode", mode, "tune", tune)
+        pl.count(mode, tune)
+        torch.cuda.synchronize()
+        gpu = pl.counts_host()
+        for t in range(len(pl.tasks)):
+            assert np.array_equal(gpu[t], refs[t]), (case, mode, tune, t)
+
+
 def test_out_of_box_coordinate_is_an_error(torch, lcmod):
     L = 1000
     xyz = torch.tensor([[1, 2, L], [3, 4, 5], [6, 7, 8]], dtype=torch.int32, device="cuda")
@@ -841,7 +895,8 @@ def _random_config(r):
     sub = [0, 1, 2, 4][int(r.integers(0, 4))]
     tune = dict(chunk=4 * int(r.integers(1, 65)),
                 waves_per_block=[0, 1, 2, 4, 8, 16][int(r.integers(0, 6))],
-                cells_per_item=int(r.integers(0, 5)))
+                cells_per_item=int(r.integers(0, 5)),
+                hist_bits=[0, 0, 16, 32][int(r.integers(0, 4))], wrap_test=int(r.integers(0, 2)))
     return dict(periodic=periodic, los=los, L=L, lo=lo, span=span, edges=edges, n_mu=n_mu, pi_max=pi_max,
                 cell=cell, sub=sub, tune=tune)
 
@@ -850,7 +905,8 @@ def _random_config(r):
 def test_random_configurations_bit_exact(torch, lcmod, oracle_mod, seed):
     """Seeded random binnings (uniform or not, e_0 >= 0, 1-59 mu bins),
     geometries (periodic boxes, open regions anywhere in |x| < 2^24),
-    lines of sight (z, midpoint, (r_p, pi)), meshes and launch shapes, on
+    lines of sight (z, midpoint, (r_p, pi)), meshes, launch shapes and
+    histogram widths (16-bit bins, some started near their wrap), on
     clustered and uniform catalogues: every task bit-exact."""
     r = np.random.default_rng(1000 + seed)
     cfg = _random_config(r)
