@@ -247,7 +247,7 @@ struct WaveState {
     int32_t nbins;            // 16-bit bins: bins of a task (slots past it are the discard slot)
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
-    uint32_t qbyte;       // LDS byte offset of qa (wave-uniform)
+    uint32_t qbyte;       // LDS byte offset of qa (wave-uniform); midpoint: qbyte / 16
     const float* pj;      // points of the task's j catalogue (wave-uniform)
     const float* ai;      // midpoint: absolute coordinates of the task's j catalogue (wave-uniform)
     uint32_t ai_last;     // midpoint: byte offset of that catalogue's last point (clamp of queued offsets)
@@ -271,6 +271,9 @@ __device__ __forceinline__ unsigned char* smem_base() { return smem; }
 // A histogram slot k 4 n_mu + 4 m then costs one 24-bit multiply-add.
 typedef __attribute__((address_space(3))) unsigned lds_u32_t;
 __device__ __forceinline__ lds_u32_t* lds_u32_at(uint32_t off) { return (lds_u32_t*)(__UINTPTR_TYPE__)off; }
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) f32x4 lds_f4_t;
+__device__ __forceinline__ lds_f4_t* lds_f4_at(uint32_t off) { return (lds_f4_t*)(__UINTPTR_TYPE__)off; }
 
 __device__ __forceinline__ void wave_sync_lds() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -585,12 +588,23 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
     if (bal) {
         if (c.acc) {
             // slot qt + (accepted lanes below this one), addressed from a
-            // wave-uniform byte base
-            const uint32_t rank =
-                __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-            const uint32_t base = w.qbyte + qt * 16u;
-            *reinterpret_cast<float4*>(smem_base() + base + rank * 16u) =
-                make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
+            // wave-uniform byte base; the midpoint kernel holds the queue's
+            // first slot in a vector register, where the lane count adds it
+            // for free (one operand fewer for the address)
+            const float4 v = make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
+            if (LOS == 1) {
+                const uint32_t slot =
+                    __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), w.qbyte));
+                // slot * 16 + qt * 16 in one instruction (the compiler would
+                // add first and shift after, two), as a plain LDS address
+                uint32_t addr;
+                asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(addr) : "v"(slot), "s"(qt * 16u));
+                *lds_f4_at(addr) = f32x4{v.x, v.y, v.z, v.w};
+            } else {
+                const uint32_t rank =
+                    __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
+                *reinterpret_cast<float4*>(smem_base() + w.qbyte + qt * 16u + rank * 16u) = v;
+            }
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
         if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0, true, H16>(w, lane, 64, qt, p, xt);
@@ -681,7 +695,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     // coordinates): there these constants go to vector registers; the other
     // kernels keep them scalar, where their vector registers are the scarcer.
     if (LOS == 1) {
-        w.qbyte = vreg(qbyte);
+        w.qbyte = vreg(qbyte >> 4);
         w.bc.mu_shift = vreg(p.mu_shift);
         w.bc.ok_m = vreg(p.ok_m);
         w.bc.nmu4 = vreg(p.nmu4);
