@@ -46,7 +46,11 @@ constexpr int kQ = 128;     // entries of the per-wave compaction queue
 static_assert(kQ >= 127, "a drain reads queue slots up to 63 + 63");
 constexpr int kX = 128;     // entries of the per-wave queue of pairs for the integer rule
 constexpr int kX16 = 64;    // the same with 16-bit bins (less LDS per wave, more waves per CU)
-constexpr int kx_for(bool h16) { return h16 ? kX16 : kX; }
+constexpr int kXm = 32;     // the same for the midpoint line of sight (32-byte entries)
+constexpr int kJ = 128;     // midpoint: rows of the per-wave j table (the swept block, then carried pairs)
+// entries of the integer-rule queue and its bytes per wave
+constexpr int kx_for(int los, bool h16) { return los == 1 ? kXm : h16 ? kX16 : kX; }
+constexpr int kx_bytes(int los, bool h16) { return kx_for(los, h16) * (los == 1 ? 32 : 16); }
 constexpr int kXcd = 8;     // queues (one per XCD)
 
 struct PcParams {
@@ -249,10 +253,12 @@ struct WaveState {
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
     uint32_t qbyte;       // LDS byte offset of qa (wave-uniform); midpoint: qbyte / 16
     const float* pj;      // points of the task's j catalogue (wave-uniform)
-    const float* ai;      // midpoint: absolute coordinates of the task's j catalogue (wave-uniform)
-    uint32_t ai_last;     // midpoint: byte offset of that catalogue's last point (clamp of queued offsets)
-    int64_t b0;           // midpoint: global index of the catalogue's first point
+    uint32_t jbyte;       // midpoint: LDS byte offset of the j table: absolute x, y, z of a j point
+                          // per 12-byte row; rows [0, 64) the swept block (row = lane), row 64 + q
+                          // the j point of queue slot q carried over from earlier blocks
+    int64_t b0;           // global index of the j catalogue's first point
     float4* xa;           // this wave's queue of pairs for the integer rule, entries [0, xn)
+    float4* xj;           // midpoint: the absolute x, y, z of each of those pairs' j point
     uint32_t xn;          // wave-uniform
     uint32_t qtail;       // wave-uniform
     uint32_t since_flush; // candidate tests this wave registered since its last flush
@@ -271,6 +277,8 @@ __device__ __forceinline__ unsigned char* smem_base() { return smem; }
 // A histogram slot k 4 n_mu + 4 m then costs one 24-bit multiply-add.
 typedef __attribute__((address_space(3))) unsigned lds_u32_t;
 __device__ __forceinline__ lds_u32_t* lds_u32_at(uint32_t off) { return (lds_u32_t*)(__UINTPTR_TYPE__)off; }
+typedef __attribute__((address_space(3))) float lds_f32_t;
+__device__ __forceinline__ lds_f32_t* lds_f32_at(uint32_t off) { return (lds_f32_t*)(__UINTPTR_TYPE__)off; }
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) f32x4 lds_f4_t;
 __device__ __forceinline__ lds_f4_t* lds_f4_at(uint32_t off) { return (lds_f4_t*)(__UINTPTR_TYPE__)off; }
@@ -289,8 +297,8 @@ __device__ __forceinline__ void wave_sync_lds() {
 // fail the test, so every value stays finite.  (A bound below 0 sends every
 // pair to the integer rule.)
 template <int LOS, bool UNIFORM, bool HAS_E0, bool FULL, bool H16>
-__device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
-                                             const PcParams& p, const BinConst& bc, float& fm, float& fr) {
+__device__ __forceinline__ uint32_t bin_fast(const float4 e, uint32_t jbyte, const PcParams& p, const BinConst& bc,
+                                             float& fm, float& fr, float3& xj) {
     // Each estimate is shifted down by its margin eps inside the FMA that
     // forms it, x' = x - eps.  Then fract(x') < 1 - 2 eps (one compare)
     // holds only when x lies in (floor(x') + eps', floor(x') + 1 - eps') with
@@ -310,18 +318,20 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
         rs = __builtin_amdgcn_rsqf(d2f);
         u = fmaf(fabsf(e.z), p.nmuf, -p.mu_shift);
     } else {
-        // l = x_i + x_j = 2 x_j - s from the j point's absolute coordinates;
-        // e.w holds their byte offset in the task's j catalogue.  A full
-        // drain reads 64 entries of the current task; a partial one clamps
-        // the offset so that a lane past the drained entries (masked by the
-        // caller) reads inside the catalogue.  l, p = s.l and q = l.l in
-        // float32, within the error bound that make_plan's mu margin covers.
-        // d2 = 0 or q = 0 give an infinite rsq and a NaN estimate, which fails.
-        const uint32_t off = FULL ? uint32_t(__float_as_int(e.w)) : min(uint32_t(__float_as_int(e.w)), ai_last);
-        const float* xj = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ai) + off);
-        const float lx = fmaf(2.0f, xj[0], -e.x);
-        const float ly = fmaf(2.0f, xj[1], -e.y);
-        const float lz = fmaf(2.0f, xj[2], -e.z);
+        // l = x_i + x_j = 2 x_j - s from the j point's absolute coordinates
+        // (returned in xj for the integer rule), read from the wave's j table
+        // at the row e.w names.  A full drain reads 64 live entries; a
+        // partial one masks the row so that a lane past the drained entries
+        // (masked by the caller) reads inside the table.  l, p = s.l and
+        // q = l.l in float32, within the error bound that make_plan's mu
+        // margin covers.  d2 = 0 or q = 0 give an infinite rsq and a NaN
+        // estimate, which fails.
+        const uint32_t jl = FULL ? uint32_t(__float_as_int(e.w)) : (uint32_t(__float_as_int(e.w)) & uint32_t(kJ - 1));
+        const lds_f32_t* row = lds_f32_at(jbyte + jl * 12u);
+        xj = make_float3(row[0], row[1], row[2]);
+        const float lx = fmaf(2.0f, xj.x, -e.x);
+        const float ly = fmaf(2.0f, xj.y, -e.y);
+        const float lz = fmaf(2.0f, xj.z, -e.z);
         const float P = fmaf(e.x, lx, fmaf(e.y, ly, e.z * lz));
         const float Q = fmaf(lx, lx, fmaf(ly, ly, lz * lz));
         d2f = fmaf(e.x, e.x, fmaf(e.y, e.y, e.z * e.z));
@@ -348,8 +358,7 @@ __device__ __forceinline__ uint32_t bin_fast(const float4 e, const float* __rest
 // Histogram slot of one queued pair by the integer rule (discard slot when it
 // lies outside [e_0, e_n)); the float64 estimates only seed the searches.
 template <int LOS, bool UNIFORM>
-__device__ __forceinline__ int exact_entry(const float4 e, const float* __restrict__ ai, uint32_t ai_last,
-                                           const ExactTab* __restrict__ xt) {
+__device__ __forceinline__ int exact_entry(const float4 e, const float4 xj, const ExactTab* __restrict__ xt) {
     const double x = e.x, y = e.y, z = e.z;
     const double d2 = fma(x, x, fma(y, y, z * z));
     const double r = sqrt(d2);
@@ -363,12 +372,11 @@ __device__ __forceinline__ int exact_entry(const float4 e, const float* __restri
         const int m_est = d2 > 0.0 ? int(fabs(z) / r * double(xt->n_mu)) : 0;
         return exact_bin_z<UNIFORM>(x, y, z, k_est, m_est, xt);
     }
-    // exact: absolute coordinates and separations are integers, l below 2^26
-    const uint32_t off = min(uint32_t(__float_as_int(e.w)), ai_last);
-    const float* xj = reinterpret_cast<const float*>(reinterpret_cast<const char*>(ai) + off);
-    const double lx = 2.0 * double(xj[0]) - x;
-    const double ly = 2.0 * double(xj[1]) - y;
-    const double lz = 2.0 * double(xj[2]) - z;
+    // exact: absolute coordinates (xj, of the j point) and separations are
+    // integers, l below 2^26
+    const double lx = 2.0 * double(xj.x) - x;
+    const double ly = 2.0 * double(xj.y) - y;
+    const double lz = 2.0 * double(xj.z) - z;
     const double P = fma(x, lx, fma(y, ly, z * lz));
     const double Q = fma(lx, lx, fma(ly, ly, lz * lz));
     const int m_est = (d2 > 0.0 && Q > 0.0) ? int(fabs(P) / sqrt(d2 * Q) * double(xt->n_mu)) : 0;
@@ -420,7 +428,7 @@ __device__ __forceinline__ uint32_t drain_exact(WaveState& w, int lane, uint32_t
     wave_sync_lds();
     const uint32_t first = xn - n;
     if (uint32_t(lane) < n) {
-        const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], w.ai, w.ai_last, xt);
+        const int bin = exact_entry<LOS, UNIFORM>(w.xa[first + lane], LOS == 1 ? w.xj[first + lane] : float4{}, xt);
         hist_add<H16>(w, uint32_t(bin) << (H16 ? 1 : 2));
         w.n_exact++;
     }
@@ -443,7 +451,8 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
     const uint32_t first = qt - n;
     const float4 e = w.qa[first + lane];
     float fm, fr;
-    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0, FULL, H16>(e, w.ai, w.ai_last, p, w.bc, fm, fr);
+    float3 xj = make_float3(0.0f, 0.0f, 0.0f);
+    const uint32_t addr = bin_fast<LOS, UNIFORM, HAS_E0, FULL, H16>(e, w.jbyte, p, w.bc, fm, fr, xj);
     const float ok_m = LOS == 1 ? w.bc.ok_m : p.ok_m;
     const bool live = uint32_t(lane) < n;
     const unsigned long long live_mask = n >= 64 ? ~0ull : ((1ull << n) - 1ull);
@@ -458,16 +467,31 @@ __device__ __forceinline__ uint32_t drain(WaveState& w, int lane, uint32_t n, ui
     if (ok && live) hist_add<H16>(w, addr);
     if (xb) {
         uint32_t xn = __builtin_amdgcn_readfirstlane(w.xn);
-        // H16 (a queue of kX16): a queue that would pass it is binned first
-        if (H16 && xn + uint32_t(__popcll(xb)) > uint32_t(kX16))
-            xn = drain_exact<LOS, UNIFORM, H16>(w, lane, xn, xn, xt);
-        if (live && !ok) {
-            const uint32_t rank =
-                __builtin_amdgcn_mbcnt_hi(uint32_t(xb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(xb), 0u));
-            w.xa[xn + rank] = e;
+        const uint32_t nx = uint32_t(__popcll(xb));
+        // a queue shorter than 128 (16-bit bins, midpoint): a queue that
+        // would pass it is binned first
+        constexpr uint32_t cap = uint32_t(kx_for(LOS, H16));
+        constexpr uint32_t batch = cap < 64u ? cap : 64u;
+        if (cap < 128u && xn + nx > cap) xn = drain_exact<LOS, UNIFORM, H16>(w, lane, xn, xn, xt);
+        if (cap < 64u && nx > cap) {
+            // (midpoint) more of them than the queue holds: bin them here
+            if (live && !ok) {
+                const int bin = exact_entry<LOS, UNIFORM>(e, make_float4(xj.x, xj.y, xj.z, 0.0f), xt);
+                hist_add<H16>(w, uint32_t(bin) << (H16 ? 1 : 2));
+                w.n_exact++;
+            }
+        } else {
+            if (live && !ok) {
+                const uint32_t rank =
+                    __builtin_amdgcn_mbcnt_hi(uint32_t(xb >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(xb), 0u));
+                w.xa[xn + rank] = e;
+                // (midpoint: with its j point's coordinates, since the j
+                // table changes before the queue is binned)
+                if (LOS == 1) w.xj[xn + rank] = make_float4(xj.x, xj.y, xj.z, 0.0f);
+            }
+            xn = __builtin_amdgcn_readfirstlane(xn + nx);
+            if (xn >= batch) xn = drain_exact<LOS, UNIFORM, H16>(w, lane, batch, xn, xt);
         }
-        xn = __builtin_amdgcn_readfirstlane(xn + uint32_t(__popcll(xb)));
-        if (xn >= 64) xn = drain_exact<LOS, UNIFORM, H16>(w, lane, 64, xn, xt);
         w.xn = xn;
     }
     wave_sync_lds();
@@ -579,8 +603,7 @@ __device__ __forceinline__ Cand test_pair(float xj, float yj, float zj, float xi
 
 // Append the accepted lanes of one candidate to the queue (length qt, kept
 // wave-uniform); bin 64 of them as soon as 64 are queued.  w4: the j point's
-// byte offset in the task's j catalogue (midpoint); the other modes queue d2
-// (r_p^2).
+// row of the j table (midpoint); the other modes queue d2 (r_p^2).
 template <int LOS, bool UNIFORM, bool HAS_E0, bool H16>
 __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, float w4, unsigned long long bal,
                                          uint32_t qt, const PcParams& p, const ExactTab* __restrict__ xt) {
@@ -612,11 +635,54 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
     return qt;
 }
 
+// Midpoint line of sight: this lane's j point of the block about to be swept
+// (i cell frame x, y, z) goes into row `lane` of the wave's j table as
+// absolute coordinates, the i cell's integer origin (ox, oy, oz) added back:
+// integers below 2^24, so the sums are exact.  The binning reads them from
+// LDS; queued pairs name the row.  Lanes without a point write values no
+// queued pair names.
+template <int LOS>
+__device__ __forceinline__ void stage_j(const WaveState& w, int lane, float x, float y, float z, float ox,
+                                        float oy, float oz) {
+    if (LOS != 1) return;
+    lds_f32_t* row = lds_f32_at(w.jbyte + uint32_t(lane) * 12u);
+    row[0] = x + ox;
+    row[1] = y + oy;
+    row[2] = z + oz;
+}
+
+// Midpoint: after a block's sweep, the pairs still queued (fewer than 64, in
+// slots [0, qtail)) that name a row of the block move their j point to row
+// 64 + slot, so the next block can take rows [0, 64).  A slot keeps its pair
+// until a drain takes it (the queue is binned from its end), so a row
+// 64 + q always belongs to the pair in slot q, and the copies (rows below
+// 64 to rows from 64) never overlap.
+template <int LOS>
+__device__ __forceinline__ void carry_j(WaveState& w, int lane) {
+    if (LOS != 1 || w.qtail == 0) return;
+    wave_sync_lds();
+    if (uint32_t(lane) < w.qtail) {
+        const uint32_t jl = uint32_t(__float_as_int(w.qa[lane].w));
+        if (jl < 64u) {
+            const uint32_t to = 64u + uint32_t(lane);
+            const lds_f32_t* src = lds_f32_at(w.jbyte + jl * 12u);
+            lds_f32_t* dst = lds_f32_at(w.jbyte + to * 12u);
+            const float a = src[0], b = src[1], c = src[2];
+            dst[0] = a;
+            dst[1] = b;
+            dst[2] = c;
+            w.qa[lane].w = __int_as_float(int(to));
+        }
+    }
+    wave_sync_lds();
+}
+
 // Four i points (ib + k .. ib + k + 3, i cell frame, read with wave-uniform
 // scalar loads) against the j block held one point per lane.  TAIL: some of
 // the four lie past the chunk (still inside the padded point array); their
 // tests are computed and their ballots cleared.  jw: this lane's j point as
-// queued for the midpoint line of sight (its byte offset, as float bits).
+// queued for the midpoint line of sight (its row of the j table, as float
+// bits).
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool TAIL, bool H16>
 __device__ __forceinline__ uint32_t sweep_group(WaveState& w, int lane, float xj, float yj, float zj,
                                                 int jrel, const float* __restrict__ q, float jw, int k,
@@ -678,7 +744,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     const ExactTab* __restrict__ xt, const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
     unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
     // LDS: [histogram, hist_stride words][control, 4 words][one queue of kQ
-    // entries per wave][one integer-rule queue of kX entries per wave]
+    // entries per wave][one integer-rule queue per wave: kX, kX16 or kXm
+    // entries][midpoint: one j table of kJ 12-byte rows per wave]
     const int lane = threadIdx.x & 63;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nwave = blockDim.x >> 6;
@@ -686,14 +753,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     WaveState w;
     w.hist = reinterpret_cast<unsigned*>(smem);
     w.pj = pts;
-    w.ai = apts;
-    w.ai_last = 0;
     w.b0 = 0;
     const uint32_t qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
     w.qa = reinterpret_cast<float4*>(smem + qbyte);
-    // The midpoint kernel holds the most scalars (its j catalogue's absolute
-    // coordinates): there these constants go to vector registers; the other
-    // kernels keep them scalar, where their vector registers are the scarcer.
+    // The midpoint kernel holds the most scalars: there these constants go
+    // to vector registers; the other kernels keep them scalar, where their
+    // vector registers are the scarcer.
     if (LOS == 1) {
         w.qbyte = vreg(qbyte >> 4);
         w.bc.mu_shift = vreg(p.mu_shift);
@@ -702,7 +767,14 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     } else {
         w.qbyte = qbyte;
     }
-    w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16) + wid * kx_for(H16);
+    constexpr int xbytes = kx_bytes(LOS, H16);
+    w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16 + wid * xbytes);
+    w.xj = w.xa + kXm;
+    {
+        const uint32_t jbyte = uint32_t(p.queue_byte0) + uint32_t(nwave) * uint32_t(kQ * 16 + xbytes) +
+                               uint32_t(wid) * uint32_t(kJ * 12);
+        w.jbyte = LOS == 1 ? vreg(jbyte) : jbyte;
+    }
     w.xn = 0;
     w.qtail = 0;
     w.since_flush = 0;
@@ -757,17 +829,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
             if (H16) w.dst = counts + int64_t(task) * p.nbins;
             // the task's j catalogue: points are gathered by their byte
             // offset from its first point (catalogues hold fewer than 2^28
-            // points); midpoint entries queued from here on hold such
-            // offsets (both queues were binned above)
+            // points)
             const int64_t cat0 = int64_t(tasks[task].y) * p.ncell * p.nsub;
             const int64_t b0 = uniform64(cs[cat0]);
             w.b0 = b0;
             w.pj = pts + 3 * b0;
-            if (LOS == 1) {
-                const int64_t b1 = uniform64(cs[cat0 + p.ncell * p.nsub]);
-                w.ai = apts + 3 * b0;
-                w.ai_last = uint32_t(max(b1 - b0, int64_t(1)) - 1) * 12u;
-            }
         }
         unsigned long long* const dst = counts + int64_t(task) * p.nbins;
         const int2 tk = tasks[task];
@@ -784,6 +850,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
         const int nsub = p.nsub, sub = p.sub;
         // this lane's sub-cell (lanes >= nsub test nothing)
         const int slx = lane % sub, sly = (lane / sub) % sub, slz = lane / (sub * sub);
+        // what a queued pair holds in place of d2 (midpoint): its j point's
+        // row in the j table, this lane
+        const float jrow = __int_as_float(lane);
         for (int c = c0; c < c1; ++c) {
             const int64_t ia0 = cs[(abase + c) * nsub], ia1 = cs[(abase + c + 1) * nsub];
             if (ia0 == ia1) continue;
@@ -837,7 +906,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                         const int n = int(min(ia1 - jb, int64_t(64)));
                         const int32_t jo = int32_t(jb - w.b0);
                         const int32_t io = int32_t(jb - ib);
-                        float x = -1e18f, y = -1e18f, z = -1e18f, wj = 0.0f;
+                        float x = -1e18f, y = -1e18f, z = -1e18f;
                         int rel = INT_MAX;
                         if (lane < n) {
                             const uint32_t off = uint32_t(lane + jo) * 12u;
@@ -847,29 +916,32 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                             y = q[1];
                             z = q[2];
                             rel = lane + io;
-                            if (LOS == 1) wj = __int_as_float(int(off));
                         }
                         account(n);
-                        sweep_block<LOS, UNIFORM, HAS_EMIN, true, H16>(w, lane, x, y, z, rel, wj, pts, ib, n_i, p, xt);
+                        stage_j<LOS>(w, lane, x, y, z, float(oix), float(oiy), float(oiz));
+                        sweep_block<LOS, UNIFORM, HAS_EMIN, true, H16>(w, lane, x, y, z, rel, jrow, pts, ib, n_i, p,
+                                                                  xt);
+                        carry_j<LOS>(w, lane);
                     }
                 }
                 // The other j points go through two stages.  Stage 1: gathered
                 // points, one per lane in lanes [0, fill): coordinates in the i
-                // cell frame and, for the midpoint line of sight, the byte
-                // offset of the point in its catalogue's absolute coordinates.
-                float sx = 0.0f, sy = 0.0f, sz = 0.0f, sw = 0.0f;
+                // cell frame.
+                float sx = 0.0f, sy = 0.0f, sz = 0.0f;
                 int fill = 0;
                 // Stage 2: the kept points, lanes [0, kfill): the block that is
                 // swept against the chunk.
-                float kx = -1e18f, ky = -1e18f, kz = -1e18f, kw = 0.0f;
+                float kx = -1e18f, ky = -1e18f, kz = -1e18f;
                 int kfill = 0;
                 auto process = [&](int nfill) {
                     const bool vj = lane < nfill;
                     // lanes past nfill hold a point far from every i point
                     const float xj = vj ? kx : -1e18f, yj = vj ? ky : -1e18f, zj = vj ? kz : -1e18f;
                     account(nfill);
-                    sweep_block<LOS, UNIFORM, HAS_EMIN, false, H16>(w, lane, xj, yj, zj, INT_MAX, kw, pts, ib, n_i, p,
-                                                               xt);
+                    stage_j<LOS>(w, lane, kx, ky, kz, float(oix), float(oiy), float(oiz));
+                    sweep_block<LOS, UNIFORM, HAS_EMIN, false, H16>(w, lane, xj, yj, zj, INT_MAX, jrow, pts, ib, n_i,
+                                                               p, xt);
+                    carry_j<LOS>(w, lane);
                 };
                 // Move the stage-1 points that lie within r_max of the chunk's
                 // box into lanes [kfill, ...) of the kept block (one cross-lane
@@ -904,13 +976,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     const float px = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sx)));
                     const float py = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sy)));
                     const float pz = __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sz)));
-                    const float pw =
-                        LOS == 1 ? __int_as_float(__builtin_amdgcn_ds_permute(to, __float_as_int(sw))) : 0.0f;
                     const bool take = lane >= kfill;
                     kx = take ? px : kx;
                     ky = take ? py : ky;
                     kz = take ? pz : kz;
-                    if (LOS == 1) kw = take ? pw : kw;
                     const int end = kfill + int(nk);
                     if (end < 64) {
                         kfill = end;
@@ -920,7 +989,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                     sx = px;
                     sy = py;
                     sz = pz;
-                    if (LOS == 1) sw = pw;
                     fill = end - 64;
                     kfill = 64;
                     return true;
@@ -985,7 +1053,6 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
                                 sx = q[0] + dox;
                                 sy = q[1] + doy;
                                 sz = q[2] + doz;
-                                if (LOS == 1) sw = __int_as_float(int(off));
                             }
                             fill += take;
                             jb += take;
@@ -1198,7 +1265,8 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
         int wpb, occ;
     };
     auto lds_of = [&](const Shape& sh, int w) {
-        return size_t(sh.queue_byte0) + size_t(w) * (kQ + kx_for(sh.h16)) * 16;
+        return size_t(sh.queue_byte0) +
+               size_t(w) * (kQ * 16 + kx_bytes(mid ? 1 : 0, sh.h16) + (mid ? kJ * 12 : 0));
     };
     auto shape_for = [&](bool h16, Shape& sh) -> lc_status {
         sh.h16 = h16;
@@ -1245,10 +1313,11 @@ static lc_status make_plan(DeviceCtx* ctx, const lc_cells* cells, const lc_task*
             // smallest on a tie: a small histogram leaves room for several
             // 4-wave blocks, a large one for a single block, which then holds
             // more waves sharing its histogram (12-wave blocks with 16-bit
-            // bins: two of them fit where one 16-wave block did)
+            // bins or the midpoint kernel's j tables: two of them fit where
+            // one 16-wave block did)
             int best = -1;
             for (int w : {4, 8, 12, 16}) {
-                if (w == 12 && !h16) continue;
+                if (w == 12 && !h16 && !mid) continue;
                 if (lds_of(sh, w) > ctx->max_lds_block) continue;
                 int o = 0;
                 LC_TRY_HIP(
