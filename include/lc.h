@@ -111,9 +111,9 @@ typedef struct {
  * Synchronises `stream` (once for a periodic box, twice for open geometry:
  * the bounding box, then the device range-check word).  A point outside the
  * geometry returns LC_ERR_RANGE and no mesh.  Every catalogue must hold
- * fewer than 2^28 points (else LC_ERR_OVERFLOW).  With LC_LOS_MID the mesh
- * also keeps the points' absolute coordinates (twice the point memory); pair
- * counting with LC_LOS_MID needs such a mesh.
+ * fewer than 2^28 points (else LC_ERR_OVERFLOW).  Any mesh of open geometry
+ * serves every line of sight (the midpoint one recovers absolute coordinates
+ * from the cell origins, exactly, since open geometry keeps |x| < 2^24).
  */
 lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const int64_t* cat_offsets,
                          int32_t n_cat, const lc_binning* b, const lc_mesh_opts* opts,

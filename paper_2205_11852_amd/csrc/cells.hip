@@ -261,11 +261,8 @@ __global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out
 // Scatter: each point goes to slot start + rank of its sub-cell (the order
 // inside a sub-cell is the counters' order, which no count depends on) and
 // is stored relative to its cell origin.
-// apts (midpoint meshes, else NULL) receives the same slot's absolute
-// coordinates, exact in float32 since open geometry keeps |x| < 2^24.
 __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint64_t* __restrict__ gid,
-                          const int64_t* __restrict__ cs, GridGeom g, float* __restrict__ pts,
-                          float* __restrict__ apts) {
+                          const int64_t* __restrict__ cs, GridGeom g, float* __restrict__ pts) {
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t gv = gid[p];
@@ -275,7 +272,6 @@ __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint
         for (int a = 0; a < 3; a++) {
             const int32_t c = axis_cell(v[a], g.lo[a], g.ext[a], g.n[a]);
             pts[3 * slot + a] = float(int64_t(v[a]) - cell_origin(c, g.lo[a], g.ext[a], g.n[a]));
-            if (apts) apts[3 * slot + a] = float(v[a]);
         }
     }
 }
@@ -293,10 +289,8 @@ using namespace lc;
 static void free_cells_mem(lc_cells* c) {
     if (!c) return;
     if (c->pts) (void)hipFree(c->pts);
-    if (c->apts) (void)hipFree(c->apts);
     if (c->cs) (void)hipFree(c->cs);
     c->pts = nullptr;
-    c->apts = nullptr;
     c->cs = nullptr;
 }
 
@@ -428,16 +422,13 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     // 4 extra points of padding: pair counting reads whole groups of four
     size_t pts_bytes = size_t(std::max<int64_t>(n_total, 1) + 4) * 3 * sizeof(float);
     size_t cs_bytes = size_t(ntot_cells + 1) * sizeof(int64_t);
-    const bool mid = b->los == LC_LOS_MID;
-    if (hipMalloc(&cells->pts, pts_bytes) != hipSuccess || hipMalloc(&cells->cs, cs_bytes) != hipSuccess ||
-        (mid && hipMalloc(&cells->apts, pts_bytes) != hipSuccess)) {
+    if (hipMalloc(&cells->pts, pts_bytes) != hipSuccess || hipMalloc(&cells->cs, cs_bytes) != hipSuccess) {
         (void)hipGetLastError();
         free_cells_mem(cells);
         delete cells;
-        return fail(LC_ERR_NOMEM, "mesh allocation (%zu + %zu bytes%s) failed", pts_bytes, cs_bytes,
-                    mid ? ", twice the points" : "");
+        return fail(LC_ERR_NOMEM, "mesh allocation (%zu + %zu bytes) failed", pts_bytes, cs_bytes);
     }
-    cells->bytes = pts_bytes * (mid ? 2 : 1) + cs_bytes;
+    cells->bytes = pts_bytes + cs_bytes;
 
     // temporaries
     int64_t* d_off = nullptr;
@@ -477,7 +468,6 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     k_zero_u32<<<grid_for(ntot_cells, 256, ctx->n_cu), 256, 0, s>>>(d_cnt, ntot_cells);
     // the padding after the last point reads as zeros
     k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(cells->pts) + 3 * n_total, 12);
-    if (mid) k_zero_u32<<<1, 64, 0, s>>>(reinterpret_cast<unsigned*>(cells->apts) + 3 * n_total, 12);
     if (n_total > 0)
         k_cell_count<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_off, d_lut, g,
                                                                        d_gid, d_cnt, d_err);
@@ -487,7 +477,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     k_scan_last<<<1, 1, 0, s>>>(cells->cs, ntot_cells, d_bsum + nblk);
     if (n_total > 0)
         k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, g,
-                                                                    cells->pts, cells->apts);
+                                                                    cells->pts);
     unsigned herr = 0;
     hipError_t e = hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s);
     dev_free(d_off, s);

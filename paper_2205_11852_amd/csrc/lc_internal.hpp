@@ -144,9 +144,6 @@ struct lc_cells {
     int32_t los = 0;
     int64_t r_max = 0;              // largest r edge the mesh was built for
     float* pts = nullptr;           // sorted points, float32 (x, y, z) relative to their cell origin
-    // midpoint meshes only: the same points' absolute coordinates (float32,
-    // exact below 2^24), read when a pair's line of sight is binned
-    float* apts = nullptr;
     // starts of the sub-cells, [n_cat][ncell][nsub] + 1 (global point index);
     // coarse cell c of catalogue k spans [cs[(k ncell + c) nsub], cs[(k ncell + c + 1) nsub])
     int64_t* cs = nullptr;

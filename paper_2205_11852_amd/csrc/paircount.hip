@@ -739,7 +739,7 @@ __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, fl
 // registers this spills outside the inner loops.
 template <int LOS, bool UNIFORM, bool HAS_EMIN, bool H16>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void k_pair_count(
-    const float* __restrict__ pts, const float* __restrict__ apts, const int64_t* __restrict__ cs,
+    const float* __restrict__ pts, const int64_t* __restrict__ cs,
     const int2* __restrict__ tasks, const int32_t* __restrict__ order, const int4* __restrict__ sten,
     const ExactTab* __restrict__ xt, const int32_t* __restrict__ otab, unsigned long long* __restrict__ counts,
     unsigned long long* __restrict__ stats, unsigned* __restrict__ queue, PcParams p) {
@@ -1090,7 +1090,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     }
 }
 
-typedef void (*PcKernel)(const float*, const float*, const int64_t*, const int2*, const int32_t*, const int4*,
+typedef void (*PcKernel)(const float*, const int64_t*, const int2*, const int32_t*, const int4*,
                          const ExactTab*, const int32_t*, unsigned long long*, unsigned long long*, unsigned*,
                          PcParams);
 
@@ -1479,12 +1479,11 @@ static void launch_plan(const Plan& pl, const lc_cells* cells, unsigned char* de
         for (int t = 0; t < pl.n_tasks; t++) {
             p.single_task = t;
             hipLaunchKernelGGL(pl.kern, dim3(pl.task_blocks[t]), dim3(pl.threads), pl.lds, s, cells->pts,
-                               cells->apts, cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st,
-                               d_q + kXcd * t, p);
+                               cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q + kXcd * t, p);
         }
     } else {
-        hipLaunchKernelGGL(pl.kern, dim3(pl.blocks), dim3(pl.threads), pl.lds, s, cells->pts, cells->apts,
-                           cells->cs, d_tasks, d_order, d_sten, d_e2, d_ot, c, st, d_q, pl.p);
+        hipLaunchKernelGGL(pl.kern, dim3(pl.blocks), dim3(pl.threads), pl.lds, s, cells->pts, cells->cs, d_tasks,
+                           d_order, d_sten, d_e2, d_ot, c, st, d_q, pl.p);
     }
 }
 
@@ -1507,7 +1506,6 @@ static std::string graph_key(const Plan& pl, const lc_cells* cells, uint64_t* co
     add(&device, sizeof device);
     add(&cells, sizeof cells);
     add(&cells->pts, sizeof cells->pts);
-    add(&cells->apts, sizeof cells->apts);
     add(&cells->cs, sizeof cells->cs);
     add(&counts, sizeof counts);
     add(&stats, sizeof stats);
@@ -1590,8 +1588,6 @@ static lc_status check_count_args(const lc_cells* cells, const lc_task* tasks, i
         return fail(LC_ERR_INVALID, "mode = %d is not LC_PERSISTENT or LC_PER_TASK (| flags)", mode);
     if (b->periodic != cells->g.periodic || (b->periodic && b->box_units != cells->g.box))
         return fail(LC_ERR_INVALID, "binning geometry differs from the mesh's");
-    if (b->los == LC_LOS_MID && !cells->apts)
-        return fail(LC_ERR_INVALID, "the midpoint line of sight needs a mesh built with the midpoint binning");
     for (int32_t t = 0; t < n_tasks; t++)
         if (tasks[t].cat_a < 0 || tasks[t].cat_a >= cells->n_cat || tasks[t].cat_b < 0 ||
             tasks[t].cat_b >= cells->n_cat)

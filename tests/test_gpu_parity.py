@@ -373,19 +373,27 @@ def test_wedge_midpoint_chunks_and_exact_mode(torch, oracle_mod, lcmod):
             assert st["exact_fallback"] >= st["binned"] > 0
 
 
-def test_midpoint_count_needs_midpoint_mesh(torch, lcmod):
-    """A mesh built for the plane-parallel binning has no absolute
-    coordinates: counting it with the midpoint binning is refused."""
+def test_midpoint_count_on_a_plane_parallel_mesh(torch, lcmod, oracle_mod):
+    """A mesh built for the plane-parallel binning of the same geometry and
+    reach also serves the midpoint binning (absolute coordinates come back
+    from the cell origins): counts bit-exact against the oracle."""
     r = np.random.default_rng(5)
-    xyz = torch.from_numpy(r.integers(1000, 200000, size=(3, 500)).astype(np.int32)).cuda()
-    off = np.array([0, 500], dtype=np.int64)
-    bz = lcmod.Binning([0, 10000, 20000], 5, False, 0, lcmod.LC_LOS_Z)
-    bm = lcmod.Binning([0, 10000, 20000], 5, False, 0, lcmod.LC_LOS_MID)
-    cells = lcmod.lc_build_cells(xyz, off, bz, 0, 0)
-    counts = torch.zeros((1, 2, 5), dtype=torch.int64, device="cuda")
-    with pytest.raises(lcmod.LcError) as ei:
-        lcmod.lc_pair_count_batch(cells, [(0, 0)], bm, counts, lcmod.LC_PERSISTENT, None)
-    assert ei.value.status == lcmod.LC_ERR_INVALID
+    xyz = r.integers(-3000000, 3000000, size=(3, 1500)).astype(np.int32)
+    xyz[2] += 6000000
+    off = np.array([0, 900, 1500], dtype=np.int64)
+    edges = [0, 100000, 250000, 400000]
+    bz = lcmod.Binning(edges, 7, False, 0, lcmod.LC_LOS_Z)
+    bm = lcmod.Binning(edges, 7, False, 0, lcmod.LC_LOS_MID)
+    cells = lcmod.lc_build_cells(torch.from_numpy(xyz).cuda(), off, bz, 0, 0)
+    tasks = [(0, 0), (0, 1), (1, 1)]
+    counts = torch.zeros((3, 3, 7), dtype=torch.int64, device="cuda")
+    lcmod.lc_pair_count_batch(cells, tasks, bm, counts, lcmod.LC_PERSISTENT, None)
+    torch.cuda.synchronize()
+    got = counts.cpu().numpy()
+    cats = [np.ascontiguousarray(xyz[:, 0:900]), np.ascontiguousarray(xyz[:, 900:1500])]
+    for t, (a, b) in enumerate(tasks):
+        ref = oracle_mod.count_pairs(cats[a], None if a == b else cats[b], edges, 7, 0, "mid")
+        assert np.array_equal(got[t], ref), t
     cells.close()
 
 
