@@ -10,7 +10,8 @@ launch with the library defaults.
 A full auto count of a 1e6-point mock is beyond the oracle (5e11 pair
 tests), so the oracle checks sampled outputs: the cross counts of a
 2048-point subset of a mock against the whole mock and against a random
-sub-catalogue, counted in the same launch as every estimator task.
+sub-catalogue, counted in the same launch as every estimator task.  For the
+wedge it also counts one whole DD task of a 3e5-point mock.
 Properties that hold at any size cover the rest:
 - the union identity DD(A u B) = DD(A) + DD(B) + DR(A, B) for a split of a
   whole mock into two halves (exact);
@@ -181,6 +182,21 @@ def test_c4_sampled_cross_counts_bit_exact(c4, oracle_mod):
 
 def test_c4_union_identity(c4):
     _check_union(c4)
+
+
+def test_c4_whole_auto_task_bit_exact(c4, oracle_mod):
+    """One whole estimator task at full size: the DD count of the last mock
+    (about 3e5 points, 4.5e10 pair tests in the oracle), every bin."""
+    pl, cats, wl = c4["pl"], c4["cats"], c4["cats"].wl
+    last = cats.n_mock - 1
+    t = int(pl.est[last][0])
+    a, b = pl.tasks[t]
+    assert a == b == last
+    _say("[c4] oracle DD of mock %d: %d points" % (last, cats.sizes()[a]))
+    ref = oracle_mod.count_pairs(cats.cat(a), None, wl.r_edges_units, wl.n_mu, 0, "mid")
+    _say("[c4] oracle done")
+    assert np.array_equal(c4["counts"][t], ref)
+    assert ref.sum() > 0
 
 
 def test_c4_counts_independent_of_tiling(c4, torch):
