@@ -107,6 +107,25 @@ int build_stencil(const GridGeom& g, int64_t r_max, int64_t pi_max, std::vector<
 // kernels
 // ---------------------------------------------------------------------------
 
+// floor(num / den) for 0 <= num < 2^53 and 0 < den, given rden = 1 / den in
+// float64: the float64 estimate lies within one of the quotient, and one
+// exact step corrects it (a 64-bit integer division is a long instruction
+// sequence on the GPU).
+__device__ inline int64_t floordiv_est(int64_t num, int64_t den, double rden) {
+    int64_t q = int64_t(double(num) * rden);
+    if (q * den > num) --q;
+    else if ((q + 1) * den <= num) ++q;
+    return q;
+}
+
+// axis_cell and cell_origin on the device, with rext = 1 / ext and rn = 1 / n
+__device__ inline int32_t axis_cell_d(int32_t x, int32_t lo, int64_t ext, int32_t n, double rext) {
+    return int32_t(floordiv_est(int64_t(x - lo) * n, ext, rext));
+}
+__device__ inline int64_t cell_origin_d(int32_t c, int32_t lo, int64_t ext, int32_t n, double rn) {
+    return int64_t(lo) + floordiv_est(int64_t(c) * ext + n - 1, n, rn);
+}
+
 // Bounding box of all points (open geometry) and the |x| < 2^24 check.
 __global__ void k_bbox(const int32_t* __restrict__ xyz, int64_t n, int32_t* __restrict__ box,
                        unsigned* __restrict__ err) {
@@ -166,6 +185,7 @@ __device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, con
 __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
                              const int32_t* __restrict__ lut, GridGeom g, uint64_t* __restrict__ gid,
                              unsigned* __restrict__ cnt, unsigned* __restrict__ err) {
+    const double r0 = 1.0 / double(g.ext[0]), r1 = 1.0 / double(g.ext[1]), r2 = 1.0 / double(g.ext[2]);
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         int32_t x = xyz[p], y = xyz[n + p], z = xyz[2 * n + p];
@@ -177,9 +197,9 @@ __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const i
             }
         }
         // fine index along each axis; coarse cell = fine / sub (the floors nest)
-        const int32_t fx = axis_cell(x, g.lo[0], g.ext[0], g.n[0] * g.sub);
-        const int32_t fy = axis_cell(y, g.lo[1], g.ext[1], g.n[1] * g.sub);
-        const int32_t fz = axis_cell(z, g.lo[2], g.ext[2], g.n[2] * g.sub);
+        const int32_t fx = axis_cell_d(x, g.lo[0], g.ext[0], g.n[0] * g.sub, r0);
+        const int32_t fy = axis_cell_d(y, g.lo[1], g.ext[1], g.n[1] * g.sub, r1);
+        const int32_t fz = axis_cell_d(z, g.lo[2], g.ext[2], g.n[2] * g.sub, r2);
         const int32_t cx = fx / g.sub, cy = fy / g.sub, cz = fz / g.sub;
         const int32_t sid = ((fz - cz * g.sub) * g.sub + (fy - cy * g.sub)) * g.sub + (fx - cx * g.sub);
         const int32_t c = find_cat(off, lut, p);
@@ -263,16 +283,27 @@ __global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out
 // is stored relative to its cell origin.
 __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint64_t* __restrict__ gid,
                           const int64_t* __restrict__ cs, GridGeom g, float* __restrict__ pts) {
+    double rext[3], rn[3];
+    for (int a = 0; a < 3; a++) {
+        rext[a] = 1.0 / double(g.ext[a]);
+        rn[a] = 1.0 / double(g.n[a]);
+    }
     for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n;
          p += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t gv = gid[p];
         if (gv == ~0ull) continue;
         const int64_t slot = cs[int64_t(gv >> 32)] + int64_t(uint32_t(gv));
         const int32_t v[3] = {xyz[p], xyz[n + p], xyz[2 * n + p]};
+        float r[3];
         for (int a = 0; a < 3; a++) {
-            const int32_t c = axis_cell(v[a], g.lo[a], g.ext[a], g.n[a]);
-            pts[3 * slot + a] = float(int64_t(v[a]) - cell_origin(c, g.lo[a], g.ext[a], g.n[a]));
+            const int32_t c = axis_cell_d(v[a], g.lo[a], g.ext[a], g.n[a], rext[a]);
+            r[a] = float(int64_t(v[a]) - cell_origin_d(c, g.lo[a], g.ext[a], g.n[a], rn[a]));
         }
+        // one 12-byte store per point
+        struct F3 {
+            float x, y, z;
+        };
+        *reinterpret_cast<F3*>(pts + 3 * slot) = F3{r[0], r[1], r[2]};
     }
 }
 
