@@ -723,15 +723,16 @@ template <int LOS, bool UNIFORM, bool HAS_EMIN, bool SELF, bool H16>
 __device__ __forceinline__ void sweep_block(WaveState& w, int lane, float xj, float yj, float zj, int jrel,
                                             float jw, const float* __restrict__ pts, int64_t ib, int n_i,
                                             const PcParams& p, const ExactTab* __restrict__ xt) {
-    ib = uniform64(ib);
+    // the group's first point, advanced 12 floats a group (a running scalar
+    // pointer, where the index arithmetic took a 64-bit multiply per group)
+    const float* q = pts + 3 * uniform64(ib);
     uint32_t qt = w.qtail;
     int k = 0;
-    for (; k + 4 <= n_i; k += 4)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false, H16>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
-                                                              k, n_i, qt, p, xt);
+    for (; k + 4 <= n_i; k += 4, q += 12)
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, false, H16>(w, lane, xj, yj, zj, jrel, q, jw, k, n_i, qt, p,
+                                                              xt);
     if (k < n_i)
-        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true, H16>(w, lane, xj, yj, zj, jrel, pts + 3 * (ib + k), jw,
-                                                             k, n_i, qt, p, xt);
+        qt = sweep_group<LOS, UNIFORM, HAS_EMIN, SELF, true, H16>(w, lane, xj, yj, zj, jrel, q, jw, k, n_i, qt, p, xt);
     w.qtail = qt;
 }
 
