@@ -440,36 +440,84 @@ __device__ __forceinline__ HhVW hh_vw(const HhPending& q, double K, int64_t i) {
 constexpr int kHhRows = 4;  // rows of A22 per k_hh_column block
 
 // WAVES waves per row: 4 while the trailing matrix is large (more loads in
-// flight), 1 once it is small (the launch's fixed cost dominates)
+// flight), 1 once it is small (the launch's fixed cost dominates).  Every
+// load that does not depend on the pending update's K (the partial sums
+// that give K, this thread's share of row k for the norm, this lane's share
+// of its row of A22 with row k beside it, the pending v and p there) is
+// issued before the first barrier and held in registers, so a launch waits
+// on memory once instead of three times in a row; elements beyond the held
+// ones (a trailing matrix wider than the block for the norm, 2 x 256 or
+// 4 x 64 per lane for the product, so that two 1024-thread blocks still fit
+// on a CU) are read afterwards.
 template <int WAVES>
-__global__ __launch_bounds__(64 * kHhRows * WAVES) void k_hh_column(double* __restrict__ W, int64_t n, int64_t k, HhPending q,
+__global__ __launch_bounds__(64 * kHhRows * WAVES)
+__attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 8 : 4))) void k_hh_column(double* __restrict__ W, int64_t n,
+                                                                          int64_t k, HhPending q,
                                                    double* __restrict__ v, double* __restrict__ tau,
                                                    double* __restrict__ d, double* __restrict__ e,
                                                    double* __restrict__ pv, double* __restrict__ vp_part) {
+    constexpr int NT = 64 * kHhRows * WAVES;   // threads
+    constexpr int NPF = 1;                     // row-k elements per thread held for the norm
+    constexpr int RPF = WAVES == 4 ? 2 : 4;    // row elements per lane held for the product
+    constexpr int64_t RST = 64 * WAVES;        // stride of a lane's row elements
     __shared__ double red[kHhRows * WAVES];
     __shared__ double wsum[kHhRows * WAVES];
     const int64_t m = n - k - 1;
     const bool pend = q.v != nullptr;
-    const double K = hh_pending_k(q, red);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t r = blockIdx.x * int64_t(kHhRows) + wv / WAVES;
+    const int64_t jl = int64_t(wv % WAVES) * 64 + lane;
+    const bool rowok = r < m;
     // row k beyond the diagonal, old values; its updated value at j is
     // x_j = row[j] - (v_0 w_{j+1} + w_0 v_{j+1}) (pending update, index 0)
     const double* row = W + k * n + k + 1;
-    const HhVW z = hh_vw(q, K, 0);
-    auto xk = [&](int64_t j, const HhVW& c) { return pend ? row[j] - (z.v * c.w + z.w * c.v) : row[j]; };
-    // four independent partial sums per thread keep several loads in flight
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t j0 = threadIdx.x; j0 < m; j0 += 4 * int64_t(blockDim.x)) {
+    double* ar = W + (k + 1 + (rowok ? r : 0)) * n + k + 1;
+    auto pv_at = [&](int64_t i) { return pend ? q.v[i] : 0.0; };
+    auto pp_at = [&](int64_t i) { return pend ? q.p[i] : 0.0; };
+    // --- loads independent of K
+    double kp = 0.0;
+    if (pend)
+        for (int64_t i = threadIdx.x; i < q.n1; i += NT) kp += q.vp_part[i];
+    const double tau_prev = pend ? *q.tau : 0.0;
+    const double zv = pv_at(0), zp = pp_at(0);
+    const double x0r = row[0], x0v = pv_at(1), x0p = pp_at(1);
+    const double yv = rowok ? pv_at(r + 1) : 0.0, yp = rowok ? pp_at(r + 1) : 0.0;
+    double nr[NPF], nv[NPF], np[NPF];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-            const int64_t j = j0 + u * int64_t(blockDim.x);
-            if (j < m) {
-                const double x = xk(j, hh_vw(q, K, j + 1));
-                s4[u] += x * x;
-            }
-        }
+    for (int t = 0; t < NPF; t++) {
+        const int64_t j = threadIdx.x + int64_t(t) * NT;
+        const bool ok = j < m;
+        nr[t] = ok ? row[j] : 0.0;
+        nv[t] = ok ? pv_at(j + 1) : 0.0;
+        np[t] = ok ? pp_at(j + 1) : 0.0;
     }
-    const double norm2 = block_sum((s4[0] + s4[1]) + (s4[2] + s4[3]), red);
-    const double x0 = xk(0, hh_vw(q, K, 1));
+    double ra[RPF], rr[RPF], rv[RPF], rp[RPF];
+#pragma unroll
+    for (int t = 0; t < RPF; t++) {
+        const int64_t j = jl + int64_t(t) * RST;
+        const bool ok = rowok && j < m;
+        ra[t] = ok ? ar[j] : 0.0;
+        rr[t] = ok ? row[j] : 0.0;
+        rv[t] = ok ? pv_at(j + 1) : 0.0;
+        rp[t] = ok ? pp_at(j + 1) : 0.0;
+    }
+    // --- K of the pending update: the same ordered reduction in every block
+    const double K = pend ? 0.5 * tau_prev * block_sum(kp, red) : 0.0;
+    const double zw = zp - K * zv;
+    // updated row k at j from the old value and the pending v, p at j + 1
+    auto xk = [&](double rj, double vj, double pj) { return pend ? rj - (zv * (pj - K * vj) + zw * vj) : rj; };
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < NPF; t++) {
+        const double x = xk(nr[t], nv[t], np[t]);
+        s += x * x;
+    }
+    for (int64_t j = threadIdx.x + int64_t(NPF) * NT; j < m; j += NT) {
+        const double x = xk(row[j], pv_at(j + 1), pp_at(j + 1));
+        s += x * x;
+    }
+    const double norm2 = block_sum(s, red);
+    const double x0 = xk(x0r, x0v, x0p);
     const double nrm = sqrt(norm2);
     const double alpha = x0 > 0 ? -nrm : nrm;   // reflect x onto alpha * e1
     const double v0 = x0 - alpha;
@@ -477,10 +525,11 @@ __global__ __launch_bounds__(64 * kHhRows * WAVES) void k_hh_column(double* __re
     const bool trivial = !(vnorm2 > 0.0) || (norm2 - x0 * x0) <= 0.0;
     const double t = trivial ? 0.0 : 2.0 / vnorm2;
     if (blockIdx.x == 0) {
-        for (int64_t i = threadIdx.x; i < m; i += blockDim.x)
-            v[i] = trivial ? 0.0 : (i == 0 ? v0 : xk(i, hh_vw(q, K, i + 1)));
+        for (int64_t i = threadIdx.x; i < m; i += NT)
+            v[i] = trivial ? 0.0 : (i == 0 ? v0 : xk(row[i], pv_at(i + 1), pp_at(i + 1)));
         if (threadIdx.x == 0) {
-            d[k] = hh_apply(W[k * n + k], q, K, 0, 0);
+            // diagonal entry k: the old one less 2 v_0 w_0 of the pending update
+            d[k] = pend ? W[k * n + k] - 2.0 * zv * zw : W[k * n + k];
             e[k] = trivial ? x0 : alpha;
             *tau = t;
         }
@@ -488,30 +537,31 @@ __global__ __launch_bounds__(64 * kHhRows * WAVES) void k_hh_column(double* __re
     // p_r = tau sum_j A22[r][j] v_j, WAVES waves per row (kHhRows rows per
     // block) taking 64 columns in turn; the row is brought up to date
     // (pending update, index r + 1) as it is read and written back
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t r = blockIdx.x * int64_t(kHhRows) + wv / WAVES;
-    const int64_t jl = int64_t(wv % WAVES) * 64 + lane;
+    const double yw = yp - K * yv;
     double acc = 0.0;
-    if (r < m) {
-        double* ar = W + (k + 1 + r) * n + k + 1;
-        const HhVW y = hh_vw(q, K, r + 1);
-        double acc4[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int64_t j0 = jl; j0 < m; j0 += 4 * 64 * WAVES) {
+    if (rowok) {
 #pragma unroll
-            for (int u = 0; u < 4; u++) {
-                const int64_t j = j0 + 64 * WAVES * u;
-                if (j < m) {
-                    const HhVW c = hh_vw(q, K, j + 1);
-                    double a = ar[j];
-                    if (pend) {
-                        a = a - (y.v * c.w + y.w * c.v);
-                        ar[j] = a;
-                    }
-                    acc4[u] += a * (j == 0 ? v0 : xk(j, c));
+        for (int tt = 0; tt < RPF; tt++) {
+            const int64_t j = jl + int64_t(tt) * RST;
+            if (j < m) {
+                const double cw = rp[tt] - K * rv[tt];
+                double a = ra[tt];
+                if (pend) {
+                    a = a - (yv * cw + yw * rv[tt]);
+                    ar[j] = a;
                 }
+                acc += a * (j == 0 ? v0 : xk(rr[tt], rv[tt], rp[tt]));
             }
         }
-        acc = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+        for (int64_t j = jl + int64_t(RPF) * RST; j < m; j += RST) {
+            const double vj = pv_at(j + 1), cw = pp_at(j + 1) - K * vj;
+            double a = ar[j];
+            if (pend) {
+                a = a - (yv * cw + yw * vj);
+                ar[j] = a;
+            }
+            acc += a * (j == 0 ? v0 : xk(row[j], vj, pp_at(j + 1)));
+        }
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     }
     if (lane == 0) wsum[wv] = acc;
@@ -525,7 +575,7 @@ __global__ __launch_bounds__(64 * kHhRows * WAVES) void k_hh_column(double* __re
             for (int w = 0; w < WAVES; w++) a += wsum[WAVES * i + w];
             const double p = trivial ? 0.0 : t * a;
             pv[ri] = p;
-            b += trivial ? 0.0 : p * (ri == 0 ? v0 : xk(ri, hh_vw(q, K, ri + 1)));
+            b += trivial ? 0.0 : p * (ri == 0 ? v0 : xk(row[ri], pv_at(ri + 1), pp_at(ri + 1)));
         }
         vp_part[blockIdx.x] = b;
     }
