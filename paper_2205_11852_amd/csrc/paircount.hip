@@ -27,9 +27,12 @@
 // in make_plan); every other pair goes to a second per-wave queue and is
 // decided by the integer rule (exact squared distances and edges, mu by
 // exact cross-multiplication), which also drops pairs that phase A's margin
-// let through.  Bins go to a uint32 LDS histogram shared by the block's
-// waves, flushed with uint64 global atomics when the block moves to another
-// task.
+// let through.  The midpoint line of sight reads each pair's x_j from a
+// per-wave LDS table of the swept j points' absolute coordinates.  Bins go
+// to an LDS histogram shared by the block's waves (uint32 bins, or two
+// 16-bit bins per word for large binnings, each wrap corrected in the
+// counts at once), flushed with uint64 global atomics when the block moves
+// to another task.
 #include <climits>
 #include <cstddef>
 #include <algorithm>
