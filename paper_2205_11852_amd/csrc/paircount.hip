@@ -254,7 +254,7 @@ struct WaveState {
     int32_t nbins;            // 16-bit bins: bins of a task (slots past it are the discard slot)
     unsigned* hist;       // the block's histogram (shared by its waves)
     float4* qa;           // this wave's queue of (sx, sy, sz, d2 | i index), entries [0, qtail)
-    uint32_t qbyte;       // LDS byte offset of qa (wave-uniform); midpoint: qbyte / 16
+    uint32_t qbyte;       // LDS slot of qa[0] (its byte offset / 16, in a vector register)
     const float* pj;      // points of the task's j catalogue (wave-uniform)
     uint32_t jbyte;       // midpoint: LDS byte offset of the j table: absolute x, y, z of a j point
                           // per 12-byte row; rows [0, 64) the swept block (row = lane), row 64 + q
@@ -272,7 +272,6 @@ struct WaveState {
 };
 
 extern __shared__ __align__(16) unsigned char smem[];
-__device__ __forceinline__ unsigned char* smem_base() { return smem; }
 
 // The LDS word at byte offset `off` of the dynamic block, addressed as the
 // plain 32-bit LDS address `off`: the pair-count kernel has no static LDS
@@ -613,24 +612,18 @@ __device__ __forceinline__ uint32_t push(WaveState& w, int lane, const Cand& c, 
     qt = __builtin_amdgcn_readfirstlane(qt);
     if (bal) {
         if (c.acc) {
-            // slot qt + (accepted lanes below this one), addressed from a
-            // wave-uniform byte base; the midpoint kernel holds the queue's
-            // first slot in a vector register, where the lane count adds it
-            // for free (one operand fewer for the address)
+            // slot qt + (accepted lanes below this one).  The queue's first
+            // slot sits in a vector register, where the lane count (mbcnt)
+            // adds it as its accumulator, and one shift-add forms the LDS
+            // address: the scalar unit, nearly as busy as the vector one
+            // here, only scales qt (the compiler's own form added the base
+            // on the scalar unit and shifted and added twice more)
             const float4 v = make_float4(c.dx, c.dy, c.dz, LOS == 1 ? w4 : c.d2);
-            if (LOS == 1) {
-                const uint32_t slot =
-                    __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), w.qbyte));
-                // slot * 16 + qt * 16 in one instruction (the compiler would
-                // add first and shift after, two), as a plain LDS address
-                uint32_t addr;
-                asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(addr) : "v"(slot), "s"(qt * 16u));
-                *lds_f4_at(addr) = f32x4{v.x, v.y, v.z, v.w};
-            } else {
-                const uint32_t rank =
-                    __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), 0u));
-                *reinterpret_cast<float4*>(smem_base() + w.qbyte + qt * 16u + rank * 16u) = v;
-            }
+            const uint32_t slot =
+                __builtin_amdgcn_mbcnt_hi(uint32_t(bal >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(bal), w.qbyte));
+            uint32_t addr;
+            asm("v_lshl_add_u32 %0, %1, 4, %2" : "=v"(addr) : "v"(slot), "s"(qt * 16u));
+            *lds_f4_at(addr) = f32x4{v.x, v.y, v.z, v.w};
         }
         qt = __builtin_amdgcn_readfirstlane(qt + uint32_t(__popcll(bal)));
         if (qt >= 64) qt = drain<LOS, UNIFORM, HAS_E0, true, H16>(w, lane, 64, qt, p, xt);
@@ -760,16 +753,15 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
     w.b0 = 0;
     const uint32_t qbyte = uint32_t(p.queue_byte0) + uint32_t(wid) * uint32_t(kQ * 16);
     w.qa = reinterpret_cast<float4*>(smem + qbyte);
-    // The midpoint kernel holds the most scalars: there these constants go
-    // to vector registers; the other kernels keep them scalar, where their
-    // vector registers are the scarcer.
+    // the queue's first slot in a vector register (the append's lane count
+    // adds it); the midpoint kernel, which holds the most scalars, also keeps
+    // its binning constants there; the other kernels keep them scalar, where
+    // their vector registers are the scarcer
+    w.qbyte = vreg(qbyte >> 4);
     if (LOS == 1) {
-        w.qbyte = vreg(qbyte >> 4);
         w.bc.mu_shift = vreg(p.mu_shift);
         w.bc.ok_m = vreg(p.ok_m);
         w.bc.nmu4 = vreg(p.nmu4);
-    } else {
-        w.qbyte = qbyte;
     }
     constexpr int xbytes = kx_bytes(LOS, H16);
     w.xa = reinterpret_cast<float4*>(smem + p.queue_byte0 + nwave * kQ * 16 + wid * xbytes);
