@@ -802,10 +802,12 @@ def test_covariance_general_parity(torch, oracle_mod, lcmod, m_a, m_b, n_split):
             assert rep["n_neg_eig"][blk] == int((wv < 0).sum())
 
 
-@pytest.mark.parametrize("P,n_split", [(1, 0), (2, 1), (3, 0), (4, 1), (5, 3), (258, 2), (300, 43)])
+@pytest.mark.parametrize("P,n_split", [(1, 0), (2, 1), (3, 0), (4, 1), (5, 3), (258, 2), (300, 43), (1100, 17)])
 def test_check_block_sizes(torch, oracle_mod, lcmod, P, n_split):
-    """The check's Householder and bisection on blocks of 1 to 298 rows (both
-    sides of the 256-row switch of the column kernel), against LAPACK."""
+    """The check's Householder and bisection on blocks of 1 to 1083 rows
+    (both sides of the 256-row switch of the column kernel, and of the
+    elements it holds in registers per lane: 512 and 1024), against
+    LAPACK."""
     n_mock = 600
     V = _synthetic_vectors(n_mock, P, 1000 + P)
     xi = torch.from_numpy(V).cuda()
