@@ -153,10 +153,12 @@ typedef struct { int32_t cat_a, cat_b; } lc_task;
 /* Tuning knobs; NULL or 0 fields = library defaults. */
 typedef struct {
     int32_t cells_per_item;   /* cells of one catalogue per work item */
-    int32_t waves_per_block;  /* 1, 2, 4, 8, 16: waves sharing a work item and a histogram.  Default:
-                                 batched, the shape with the most resident waves per CU (4, unless a
-                                 large histogram leaves LDS for one block only); LC_PER_TASK, 16 (a
-                                 single task's few items finish sooner with more waves each) */
+    int32_t waves_per_block;  /* 1, 2, 4, 8, 12, 16: waves sharing a work item and a histogram.
+                                 Default: batched, the shape with the most resident waves per CU,
+                                 the smallest on a tie (4, unless a large histogram leaves LDS for
+                                 fewer blocks; 12 is tried with 16-bit bins and for the midpoint
+                                 line of sight); LC_PER_TASK, 16 (a single task's few items finish
+                                 sooner with more waves each) */
     int32_t blocks_per_cu;    /* persistent grid = CUs * blocks_per_cu (<= occupancy) */
     int32_t chunk;            /* i points tested together against each gathered j set:
                                  a multiple of 4 in [4, 256];
