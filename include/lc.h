@@ -96,7 +96,15 @@ typedef struct {
     int32_t sub;              /* sub-cells per axis inside a coarse cell: 1, 2 or 4
                                  (default 2); pair counting skips the sub-cells that
                                  lie beyond r_max of each group of 64 points */
-    int32_t reserved[2];
+    int32_t arrival_order;    /* 0 (default): the points of a sub-cell are stored in
+                                 (x, y, z) order, so the mesh, and the candidate tests
+                                 counted in stats, depend only on the catalogues (a
+                                 pass quadratic in each sub-cell's size and a 16-byte
+                                 staging record per point during the build); 1: in
+                                 the order the build's atomic counters hand out, which
+                                 can change from run to run.  Counts are exact either
+                                 way */
+    int32_t reserved;
 } lc_mesh_opts;
 
 /*

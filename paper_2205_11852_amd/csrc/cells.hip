@@ -2,7 +2,8 @@
 // cells, so that pair counting only visits cells that can hold pairs closer
 // than r_max.  Steps: (open geometry) bounding box -> cell id and per-cell
 // histogram -> exclusive scan -> scatter of the points as float32 values
-// relative to their cell's integer origin.
+// relative to their cell's integer origin -> a fixed order inside each
+// sub-cell.
 #include <algorithm>
 #include <cmath>
 
@@ -178,10 +179,10 @@ __device__ __forceinline__ int32_t find_cat(const int64_t* __restrict__ off, con
     return c;
 }
 
-// Cell id per point, its rank within the sub-cell (the returned value of the
-// per-cell counter), packed as id << 32 | rank (sub-cell ids are below
-// 2^31), and the per-cell histogram; range check for periodic boxes (an
-// out-of-range point gets ~0).
+// Cell id per point, its arrival rank within the sub-cell (the returned
+// value of the per-cell counter, which varies from run to run), packed as
+// id << 32 | rank (sub-cell ids are below 2^31), and the per-cell histogram;
+// range check for periodic boxes (an out-of-range point gets ~0).
 __global__ void k_cell_count(const int32_t* __restrict__ xyz, int64_t n, const int64_t* __restrict__ off,
                              const int32_t* __restrict__ lut, GridGeom g, uint64_t* __restrict__ gid,
                              unsigned* __restrict__ cnt, unsigned* __restrict__ err) {
@@ -278,11 +279,17 @@ __global__ void k_scan_down(const unsigned* __restrict__ cnt, int64_t n, const i
 
 __global__ void k_scan_last(int64_t* out, int64_t n, const int64_t* grand) { out[n] = *grand; }
 
-// Scatter: each point goes to slot start + rank of its sub-cell (the order
-// inside a sub-cell is the counters' order, which no count depends on) and
-// is stored relative to its cell origin.
+struct F3 {
+    float x, y, z;
+};
+
+// Scatter: each point, as float32 offsets from its coarse cell's integer
+// origin, goes to its sub-cell's slot for its arrival rank: one 12-byte
+// store into the mesh, or (STAGE, for a fixed order) a 16-byte record with
+// the sub-cell id as its fourth word into the staging array.
+template <bool STAGE>
 __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint64_t* __restrict__ gid,
-                          const int64_t* __restrict__ cs, GridGeom g, float* __restrict__ pts) {
+                          const int64_t* __restrict__ cs, GridGeom g, void* __restrict__ out) {
     double rext[3], rn[3];
     for (int a = 0; a < 3; a++) {
         rext[a] = 1.0 / double(g.ext[a]);
@@ -299,11 +306,46 @@ __global__ void k_scatter(const int32_t* __restrict__ xyz, int64_t n, const uint
             const int32_t c = axis_cell_d(v[a], g.lo[a], g.ext[a], g.n[a], rext[a]);
             r[a] = float(int64_t(v[a]) - cell_origin_d(c, g.lo[a], g.ext[a], g.n[a], rn[a]));
         }
-        // one 12-byte store per point
-        struct F3 {
-            float x, y, z;
-        };
-        *reinterpret_cast<F3*>(pts + 3 * slot) = F3{r[0], r[1], r[2]};
+        if (STAGE)
+            static_cast<float4*>(out)[slot] = make_float4(r[0], r[1], r[2], __int_as_float(int32_t(gv >> 32)));
+        else
+            static_cast<F3*>(out)[slot] = F3{r[0], r[1], r[2]};
+    }
+}
+
+// Fixed order inside every sub-cell (the default; lc_mesh_opts.arrival_order
+// skips it): the point in staging slot t goes to rank = the number of its
+// sub-cell's points that precede it in (x, y, z) order, points with equal
+// coordinates ranked by slot; equal points are the same three floats, so the
+// stored mesh does not depend on the arrival order.  Each point reads its
+// whole sub-cell (consecutive slots, so the lanes of a wave mostly read the
+// same record): quadratic in the sub-cell's size, like the pair count's own
+// work there.
+__device__ __forceinline__ int before(const float4 q, const float4 me, int rq, int rm) {
+    return q.x < me.x || (q.x == me.x && (q.y < me.y || (q.y == me.y && (q.z < me.z ||
+                                                                        (q.z == me.z && rq < rm)))));
+}
+
+__global__ void k_order(int64_t ntot_cells, const int64_t* __restrict__ cs, const float4* __restrict__ stage,
+                        F3* __restrict__ pts) {
+    // slots [0, cs[ntot_cells]) are filled (a periodic point out of the box
+    // has none: that build fails after this launch)
+    const int64_t n = cs[ntot_cells];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const float4 me = stage[t];
+        const int64_t id = __float_as_int(me.w);
+        const int64_t s0 = cs[id];
+        const float4* seg = stage + s0;
+        const int c = int(cs[id + 1] - s0), my = int(t - s0);
+        int rank = 0, u = 0;
+        for (; u + 4 <= c; u += 4) {
+            const float4 q0 = seg[u], q1 = seg[u + 1], q2 = seg[u + 2], q3 = seg[u + 3];
+            rank += before(q0, me, u, my) + before(q1, me, u + 1, my) + before(q2, me, u + 2, my) +
+                    before(q3, me, u + 3, my);
+        }
+        for (; u < c; u++) rank += before(seg[u], me, u, my);
+        pts[s0 + rank] = F3{me.x, me.y, me.z};
     }
 }
 
@@ -356,7 +398,11 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     LC_TRY(check_binning(b));
     const int32_t cell_units = opts ? opts->cell_units : 0;
     int32_t sub = opts && opts->sub ? opts->sub : 2;
+    const int32_t arrival_order = opts ? opts->arrival_order : 0;
     if (sub != 1 && sub != 2 && sub != 4) return fail(LC_ERR_INVALID, "sub = %d, must be 1, 2 or 4", sub);
+    if (arrival_order != 0 && arrival_order != 1)
+        return fail(LC_ERR_INVALID, "arrival_order = %d, must be 0 or 1", arrival_order);
+    const bool fixed_order = arrival_order == 0;
     if (n_cat < 1) return fail(LC_ERR_INVALID, "n_cat = %d, must be >= 1", n_cat);
     if (!cat_offsets) return fail(LC_ERR_INVALID, "cat_offsets is NULL");
     if (n_total < 0) return fail(LC_ERR_INVALID, "n_total < 0");
@@ -465,6 +511,7 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     int64_t* d_off = nullptr;
     const int32_t* d_lut = nullptr;
     uint64_t* d_gid = nullptr;
+    float4* d_stage = nullptr;
     unsigned* d_cnt = nullptr;
     int64_t* d_bsum = nullptr;
     const int64_t nblk = (ntot_cells + kScanTile - 1) / kScanTile;
@@ -486,11 +533,14 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
         if (st == LC_OK) d_lut = reinterpret_cast<const int32_t*>(reinterpret_cast<unsigned char*>(d_off) + lut_off);
     }
     if (st == LC_OK) st = dev_alloc((void**)&d_gid, sizeof(uint64_t) * std::max<int64_t>(n_total, 1), s);
+    if (st == LC_OK && fixed_order)
+        st = dev_alloc((void**)&d_stage, sizeof(float4) * std::max<int64_t>(n_total, 1), s);
     if (st == LC_OK) st = dev_alloc((void**)&d_cnt, sizeof(unsigned) * ntot_cells, s);
     if (st == LC_OK) st = dev_alloc((void**)&d_bsum, sizeof(int64_t) * (nblk + 1), s);
     if (st != LC_OK) {
         dev_free(d_off, s);
         dev_free(d_gid, s);
+        dev_free(d_stage, s);
         dev_free(d_cnt, s);
         dev_free(d_bsum, s);
         lc_free_cells(cells);
@@ -506,13 +556,20 @@ extern "C" lc_status lc_build_cells(const int32_t* xyz, int64_t n_total, const i
     k_scan_top<<<1, kScanThreads, 0, s>>>(d_bsum, nblk, d_bsum + nblk);
     k_scan_down<<<nblk, kScanThreads, 0, s>>>(d_cnt, ntot_cells, d_bsum, cells->cs);
     k_scan_last<<<1, 1, 0, s>>>(cells->cs, ntot_cells, d_bsum + nblk);
-    if (n_total > 0)
-        k_scatter<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, g,
-                                                                    cells->pts);
+    if (n_total > 0 && fixed_order) {
+        k_scatter<true><<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs, g,
+                                                                          d_stage);
+        k_order<<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(ntot_cells, cells->cs, d_stage,
+                                                                  reinterpret_cast<F3*>(cells->pts));
+    } else if (n_total > 0) {
+        k_scatter<false><<<grid_for(n_total, 256, ctx->n_cu), 256, 0, s>>>(xyz, n_total, d_gid, cells->cs,
+                                                                           g, cells->pts);
+    }
     unsigned herr = 0;
     hipError_t e = hipMemcpyAsync(&herr, d_err, sizeof herr, hipMemcpyDeviceToHost, s);
     dev_free(d_off, s);
     dev_free(d_gid, s);
+    dev_free(d_stage, s);
     dev_free(d_cnt, s);
     dev_free(d_bsum, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

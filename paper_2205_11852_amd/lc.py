@@ -66,7 +66,7 @@ class lc_tuning(ctypes.Structure):
 
 class lc_mesh_opts(ctypes.Structure):
     _fields_ = [("cell_units", ctypes.c_int32), ("sub", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("arrival_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class lc_cells_info(ctypes.Structure):
@@ -269,16 +269,16 @@ class Cells:
 
 
 def lc_build_cells(xyz, cat_offsets, binning: Binning, cell_units: int = 0, sub: int = 0,
-                   stream=None) -> Cells:
+                   stream=None, arrival_order: bool = False) -> Cells:
     """xyz: int32 device tensor [3, n_total]; cat_offsets: int64 [n_cat+1];
-    cell_units / sub: mesh options (0 = library defaults)."""
+    cell_units / sub / arrival_order: mesh options (0 = library defaults)."""
     off = np.ascontiguousarray(np.asarray(cat_offsets, dtype=np.int64))
     n_total = int(off[-1]) if len(off) else 0
     if xyz is not None and not isinstance(xyz, int):
         if tuple(xyz.shape) != (3, n_total) or str(xyz.dtype) != "torch.int32" or not xyz.is_contiguous():
             raise ValueError("xyz must be a contiguous int32 tensor of shape (3, %d)" % n_total)
     out = ctypes.c_void_p()
-    opts = lc_mesh_opts(int(cell_units), int(sub))
+    opts = lc_mesh_opts(int(cell_units), int(sub), int(arrival_order))
     _check(lib().lc_build_cells(_dptr(xyz), n_total, off.ctypes.data, len(off) - 1,
                                 ctypes.byref(binning.c), ctypes.byref(opts), _stream(stream),
                                 ctypes.byref(out)))

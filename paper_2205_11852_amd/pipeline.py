@@ -130,12 +130,13 @@ class Pipeline:
         self.tuned = lc.lc_autotune(self.xyz, self.offsets, self.binning, self.tasks, sample_tasks)
         return self.tuned
 
-    def build_cells(self, cell_units: int = 0, sub: int = 0):
+    def build_cells(self, cell_units: int = 0, sub: int = 0, arrival_order: bool = False):
         if self.cells is not None:
             self.cells.close()
         if self.tuned is not None and cell_units == 0 and sub == 0:
             cell_units, sub = self.tuned["cell_units"], self.tuned["sub"]
-        self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units, sub)
+        self.cells = lc.lc_build_cells(self.xyz, self.offsets, self.binning, cell_units, sub,
+                                       arrival_order=arrival_order)
         return self.cells
 
     def count(self, mode: int = lc.LC_PERSISTENT, tune: Optional[dict] = None, zero: bool = True):

@@ -81,7 +81,7 @@ def test_build_cells_rejects_bad_options(L):
     b = _binning()
     off = np.array([0, 4], dtype=np.int64)
     h = ctypes.c_void_p()
-    for opts in (lc.lc_mesh_opts(0, 3), lc.lc_mesh_opts(-5, 0)):
+    for opts in (lc.lc_mesh_opts(0, 3), lc.lc_mesh_opts(-5, 0), lc.lc_mesh_opts(0, 0, 2)):
         st = L.lc_build_cells(0x1000, 4, off.ctypes.data, 1, ctypes.byref(b.c), ctypes.byref(opts), None,
                               ctypes.byref(h))
         assert st == lc.LC_ERR_INVALID

@@ -166,6 +166,33 @@ def test_c1_cell_sizes_identical(c1, torch, cell_mpc, sub):
     pl.build_cells()
 
 
+@pytest.mark.parametrize("cell_mpc,sub", [(0.0, 0), (50.0, 2), (240.0, 4)])
+def test_mesh_order_does_not_depend_on_arrival(c1, torch, cell_mpc, sub):
+    """The mesh stores each sub-cell's points in (x, y, z) order, so a mesh built from the same catalogues with every catalogue's
+    points shuffled (which changes the order in which points reach their
+    sub-cells) leads to the same candidate tests, not only the same counts.
+    Coarse cells put hundreds of points in one sub-cell."""
+    from paper_2205_11852_amd.pipeline import Pipeline
+    cats = c1["cats"]
+    r = np.random.default_rng(11)
+    xyz = cats.xyz.copy()
+    for c in range(cats.n_cat):
+        a, b = cats.offsets[c], cats.offsets[c + 1]
+        xyz[:, a:b] = xyz[:, a + r.permutation(b - a)]
+    shuffled = dataclasses.replace(cats, xyz=np.ascontiguousarray(xyz))
+    seen = []
+    for cs in (cats, shuffled, cats):
+        pl = Pipeline(cs)
+        pl.build_cells(int(cell_mpc * mockgen.UNITS_PER_MPC), sub)
+        pl.count()
+        torch.cuda.synchronize()
+        assert np.array_equal(pl.counts_host(), c1["ref"]), (cell_mpc, sub)
+        st = pl.stats_host()
+        seen.append((st["candidates"], st["binned"]))
+    _say("[order] cell", cell_mpc, "sub", sub, "candidates", seen)
+    assert seen[0] == seen[1] == seen[2]
+
+
 def test_edge_pairs_gpu(torch, lcmod):
     """Hand-derived bins of pairs exactly on r and mu edges (tests/golden)."""
     for scale in (1, 4096, 2 ** 18 // 5):
@@ -423,7 +450,8 @@ def test_slab_open_geometry_bit_exact(torch, oracle_mod, lcmod):
 
 def test_ragged_catalogues(torch, oracle_mod, lcmod):
     """Empty and one-point catalogues, coincident points, points on the box
-    faces, everything in one cell, non-uniform edges with e_0 > 0."""
+    faces, everything in one cell, non-uniform edges with e_0 > 0; arrival
+    and fixed mesh order."""
     L = 1 << 16
     r = np.random.default_rng(5)
     cats = [np.zeros((3, 0), np.int32), np.array([[5], [6], [7]], np.int32),
@@ -437,7 +465,7 @@ def test_ragged_catalogues(torch, oracle_mod, lcmod):
     for edges in ([0, 100, 900, 2000, 3000, 6000], [40, 50, 64, 1000, 1001, 4321, 9000]):
         for n_mu in (1, 3, 10):
             bn = lcmod.Binning(edges, n_mu, True, L, lcmod.LC_LOS_Z)
-            cells = lcmod.lc_build_cells(xyz, off, bn, sub=(1, 2, 4)[n_mu % 3])
+            cells = lcmod.lc_build_cells(xyz, off, bn, sub=(1, 2, 4)[n_mu % 3], arrival_order=n_mu == 1)
             counts = torch.zeros((len(tasks), bn.n_r, n_mu), dtype=torch.int64, device="cuda")
             lcmod.lc_pair_count_batch(cells, tasks, bn, counts)
             got = counts.cpu().numpy().view(np.uint64)
@@ -915,9 +943,10 @@ def _random_config(r):
 def test_random_configurations_bit_exact(torch, lcmod, oracle_mod, seed):
     """Seeded random binnings (uniform or not, e_0 >= 0, 1-59 mu bins),
     geometries (periodic boxes, open regions anywhere in |x| < 2^24),
-    lines of sight (z, midpoint, (r_p, pi)), meshes, launch shapes and
-    histogram widths (16-bit bins, some started near their wrap), on
-    clustered and uniform catalogues: every task bit-exact."""
+    lines of sight (z, midpoint, (r_p, pi)), meshes (odd seeds in arrival
+    order), launch shapes and histogram widths (16-bit bins, some started
+    near their wrap), on clustered and uniform catalogues: every task
+    bit-exact."""
     r = np.random.default_rng(1000 + seed)
     cfg = _random_config(r)
     _say("[random]", seed, {k: v for k, v in cfg.items() if k != "edges"}, "n_r", len(cfg["edges"]) - 1)
@@ -935,7 +964,7 @@ def test_random_configurations_bit_exact(torch, lcmod, oracle_mod, seed):
     xyz = torch.from_numpy(np.ascontiguousarray(np.concatenate(cats, axis=1))).cuda()
     los = {"z": lcmod.LC_LOS_Z, "mid": lcmod.LC_LOS_MID, "rppi": lcmod.LC_LOS_RPPI}[cfg["los"]]
     bn = lcmod.Binning(cfg["edges"], cfg["n_mu"], cfg["periodic"], cfg["L"], los, cfg["pi_max"])
-    cells = lcmod.lc_build_cells(xyz, off, bn, cfg["cell"], cfg["sub"])
+    cells = lcmod.lc_build_cells(xyz, off, bn, cfg["cell"], cfg["sub"], arrival_order=seed % 2 == 1)
     tasks = [(a, b) for a in range(3) for b in range(3)]
     counts = torch.zeros((len(tasks), bn.n_r, bn.n_mu), dtype=torch.int64, device="cuda")
     lcmod.lc_pair_count_batch(cells, tasks, bn, counts, lcmod.LC_PERSISTENT, cfg["tune"])
