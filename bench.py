@@ -48,12 +48,13 @@ def _code_only(src: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """sha256[:16] of the pair-count kernel's code (paircount.hip and
-    lc_internal.hpp, comments and layout removed, so that only a change to
-    the code invalidates the measured traffic)."""
+    """sha256[:16] of the pair-count kernel's code and of the mesh build
+    whose layout it reads (paircount.hip, lc_internal.hpp and cells.hip,
+    comments and layout removed, so that only a change to the code
+    invalidates the measured traffic)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("paircount.hip", "lc_internal.hpp"):
+    for f in ("paircount.hip", "lc_internal.hpp", "cells.hip"):
         with open(os.path.join(ROOT, "paper_2205_11852_amd", "csrc", f)) as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
