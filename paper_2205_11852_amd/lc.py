@@ -196,6 +196,16 @@ def _dptr(t) -> Optional[int]:
     return int(t.data_ptr())
 
 
+def _need(t, n_elems: int, name: str):
+    """Refuse a torch tensor smaller than the n_elems float64 values the call
+    reads or writes through it (raw pointers and None are passed through)."""
+    if t is None or isinstance(t, int):
+        return
+    if not t.is_contiguous() or t.numel() * t.element_size() < int(n_elems) * 8:
+        raise ValueError("%s must be a contiguous tensor of at least %d float64 values (got %s, %s)"
+                         % (name, int(n_elems), tuple(t.shape), t.dtype))
+
+
 def _stream(stream) -> Optional[int]:
     if stream is None:
         try:
@@ -331,6 +341,10 @@ def lc_xi_multipoles(counts, tasks, cat_sizes, est, n_r: int, n_mu: int, xi, str
 
 def lc_covariance(xi, n_mock: int, n_r: int, n_mu: int, m_a: int, M: float, precision: int,
                   A, B, C, report: bool = True, stream=None) -> Optional[dict]:
+    P = int(n_r) * int(n_mu) + 3 * int(n_r)
+    _need(xi, int(n_mock) * 3 * P, "xi")
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        _need(t, P * P, name)
     rep = lc_cov_report() if report else None
     _check(lib().lc_covariance(_dptr(xi), int(n_mock), int(n_r), int(n_mu), int(m_a), float(M),
                                int(precision), _dptr(A), _dptr(B), _dptr(C),
@@ -353,6 +367,9 @@ def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, 
 
 def lc_covariance_general(xi, n_mock: int, P: int, n_split: int, m_a: float, m_b: float, M: float,
                           precision: int, A, B, C, report: bool = True, stream=None) -> Optional[dict]:
+    _need(xi, int(n_mock) * 3 * int(P), "xi")
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        _need(t, int(P) * int(P), name)
     rep = lc_cov_report() if report else None
     _check(lib().lc_covariance_general(_dptr(xi), int(n_mock), int(P), int(n_split), float(m_a), float(m_b),
                                        float(M), int(precision), _dptr(A), _dptr(B), _dptr(C),
@@ -391,6 +408,8 @@ def lc_map_matrix(X, P_in: int, group, weight, P_out: int, Y, stream=None):
 
 
 def lc_sample_covariance(x, n_mock: int, P: int, precision: int, C, stream=None):
+    _need(x, int(n_mock) * int(P), "x")
+    _need(C, int(P) * int(P), "C")
     _check(lib().lc_sample_covariance(_dptr(x), int(n_mock), int(P), int(precision), _dptr(C),
                                       _stream(stream)))
 

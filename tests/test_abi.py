@@ -262,3 +262,20 @@ def test_map_builders_reject_bad_arguments(L):
     assert L.lc_map_projected(4, 5, float("inf"), g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
     assert L.lc_map_rebin_blocks(3, 0, 2, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
     assert L.lc_map_rebin_blocks(3, 4, 0, g.ctypes.data, w.ctypes.data, ctypes.byref(P)) == lc.LC_ERR_INVALID
+
+
+def test_binding_refuses_short_buffers():
+    """The Python binding checks tensor sizes before handing raw pointers to
+    the library (which cannot): an [n_mock][P] array passed where the
+    [n_mock][3][P] layout is read, or a short output matrix, is an error."""
+    import torch
+    n_r, n_mu, n_mock = 4, 5, 10
+    P = n_r * n_mu + 3 * n_r
+    xi = torch.zeros((n_mock, P), dtype=torch.float64)
+    C = torch.zeros((P, P), dtype=torch.float64)
+    with pytest.raises(ValueError, match="xi"):
+        lc.lc_covariance(xi, n_mock, n_r, n_mu, 1, 50.0, lc.LC_FP64, None, None, C, report=False)
+    with pytest.raises(ValueError, match="xi"):
+        lc.lc_covariance_general(xi, n_mock, P, 0, 1.0, 2.0, 50.0, lc.LC_FP64, None, None, C, report=False)
+    with pytest.raises(ValueError, match="C"):
+        lc.lc_sample_covariance(xi, n_mock, P, lc.LC_FP64, C[:-1])
