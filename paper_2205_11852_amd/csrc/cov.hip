@@ -448,7 +448,8 @@ constexpr int kHhRows = 4;  // rows of A22 per k_hh_column block
 // on memory once instead of three times in a row; elements beyond the held
 // ones (a trailing matrix wider than the block for the norm, 2 x 256 or
 // 4 x 64 per lane for the product, so that two 1024-thread blocks still fit
-// on a CU) are read afterwards.
+// on a CU) are read afterwards, the product's two per lane at a time with
+// both loads issued before either store (four at a time spill registers).
 template <int WAVES>
 __global__ __launch_bounds__(64 * kHhRows * WAVES)
 __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 8 : 4))) void k_hh_column(double* __restrict__ W, int64_t n,
@@ -460,6 +461,7 @@ __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 8 : 4))) void k_hh_column(double
     constexpr int NPF = 1;                     // row-k elements per thread held for the norm
     constexpr int RPF = WAVES == 4 ? 2 : 4;    // row elements per lane held for the product
     constexpr int64_t RST = 64 * WAVES;        // stride of a lane's row elements
+    constexpr int CH = 2;                      // row elements per load group after the held ones
     __shared__ double red[kHhRows * WAVES];
     __shared__ double wsum[kHhRows * WAVES];
     const int64_t m = n - k - 1;
@@ -512,6 +514,7 @@ __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 8 : 4))) void k_hh_column(double
         const double x = xk(nr[t], nv[t], np[t]);
         s += x * x;
     }
+#pragma unroll 2
     for (int64_t j = threadIdx.x + int64_t(NPF) * NT; j < m; j += NT) {
         const double x = xk(row[j], pv_at(j + 1), pp_at(j + 1));
         s += x * x;
@@ -553,14 +556,32 @@ __attribute__((amdgpu_waves_per_eu(WAVES == 4 ? 8 : 4))) void k_hh_column(double
                 acc += a * (j == 0 ? v0 : xk(rr[tt], rv[tt], rp[tt]));
             }
         }
-        for (int64_t j = jl + int64_t(RPF) * RST; j < m; j += RST) {
-            const double vj = pv_at(j + 1), cw = pp_at(j + 1) - K * vj;
-            double a = ar[j];
-            if (pend) {
-                a = a - (yv * cw + yw * vj);
-                ar[j] = a;
+        // the rest in groups of CH elements whose loads are all issued
+        // before the group's stores (same order of the sum)
+        for (int64_t j0 = jl + int64_t(RPF) * RST; j0 < m; j0 += CH * RST) {
+            double ca[CH], cr[CH], cv[CH], cp[CH];
+#pragma unroll
+            for (int u = 0; u < CH; u++) {
+                const int64_t j = j0 + int64_t(u) * RST;
+                const bool ok = j < m;
+                ca[u] = ok ? ar[j] : 0.0;
+                cr[u] = ok ? row[j] : 0.0;
+                cv[u] = ok ? pv_at(j + 1) : 0.0;
+                cp[u] = ok ? pp_at(j + 1) : 0.0;
             }
-            acc += a * (j == 0 ? v0 : xk(row[j], vj, pp_at(j + 1)));
+#pragma unroll
+            for (int u = 0; u < CH; u++) {
+                const int64_t j = j0 + int64_t(u) * RST;
+                if (j < m) {
+                    const double cw = cp[u] - K * cv[u];
+                    double a = ca[u];
+                    if (pend) {
+                        a = a - (yv * cw + yw * cv[u]);
+                        ar[j] = a;
+                    }
+                    acc += a * (j == 0 ? v0 : xk(cr[u], cv[u], cp[u]));
+                }
+            }
         }
         for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
     }
