@@ -197,13 +197,19 @@ def _dptr(t) -> Optional[int]:
 
 
 def _need(t, n_elems: int, name: str):
-    """Refuse a torch tensor smaller than the n_elems float64 values the call
-    reads or writes through it (raw pointers and None are passed through)."""
+    """Refuse a torch tensor smaller than the n_elems 8-byte values (float64
+    or uint64) the call reads or writes through it; raw pointers and None
+    are passed through."""
     if t is None or isinstance(t, int):
         return
     if not t.is_contiguous() or t.numel() * t.element_size() < int(n_elems) * 8:
-        raise ValueError("%s must be a contiguous tensor of at least %d float64 values (got %s, %s)"
+        raise ValueError("%s must be a contiguous tensor of at least %d 8-byte values (got %s, %s)"
                          % (name, int(n_elems), tuple(t.shape), t.dtype))
+
+
+def _rows(n: int, ld: int, width: int) -> int:
+    """Values spanned by n rows of `width` values at stride ld (0: width)."""
+    return 0 if int(n) <= 0 else (int(n) - 1) * (int(ld) or int(width)) + int(width)
 
 
 def _stream(stream) -> Optional[int]:
@@ -334,6 +340,8 @@ def lc_xi_multipoles(counts, tasks, cat_sizes, est, n_r: int, n_mu: int, xi, str
     t = tasks_array(tasks)
     sz = np.ascontiguousarray(np.asarray(cat_sizes, dtype=np.int64))
     e = np.ascontiguousarray(np.asarray(est, dtype=np.int32).reshape(-1, 5))
+    _need(counts, len(t) * int(n_r) * int(n_mu), "counts")
+    _need(xi, len(e) * 3 * (int(n_r) * int(n_mu) + 3 * int(n_r)), "xi")
     _check(lib().lc_xi_multipoles(_dptr(counts), t.ctypes.data, len(t), sz.ctypes.data, len(sz),
                                   e.ctypes.data, len(e), int(n_r), int(n_mu), _dptr(xi),
                                   _stream(stream)))
@@ -360,6 +368,8 @@ def lc_xi_split(counts, tasks, cat_sizes, est, n_sub: int, n_r: int, n_mu: int, 
     t = tasks_array(tasks)
     sz = np.ascontiguousarray(np.asarray(cat_sizes, dtype=np.int64))
     e = np.ascontiguousarray(np.asarray(est, dtype=np.int32).reshape(-1, 1 + 2 * int(n_sub)))
+    _need(counts, len(t) * int(n_r) * int(n_mu), "counts")
+    _need(xi, int(offset) + _rows(len(e), ld_xi, int(n_r) * int(n_mu) + 3 * int(n_r)), "xi")
     _check(lib().lc_xi_split(_dptr(counts), t.ctypes.data, len(t), sz.ctypes.data, len(sz), e.ctypes.data,
                              int(n_sub), len(e), int(n_r), int(n_mu), _dptr(xi) + 8 * int(offset), int(ld_xi),
                              _stream(stream)))
@@ -378,6 +388,9 @@ def lc_covariance_general(xi, n_mock: int, P: int, n_split: int, m_a: float, m_b
 
 
 def lc_rebin_counts(counts, n_tasks: int, n_r: int, n_mu: int, w_r: int, w_mu: int, out, stream=None):
+    _need(counts, int(n_tasks) * int(n_r) * int(n_mu), "counts")
+    if int(w_r) >= 1 and int(w_mu) >= 1:
+        _need(out, int(n_tasks) * (-(-int(n_r) // int(w_r))) * (int(n_mu) // int(w_mu)), "out")
     _check(lib().lc_rebin_counts(_dptr(counts), int(n_tasks), int(n_r), int(n_mu), int(w_r), int(w_mu),
                                  _dptr(out), _stream(stream)))
 
@@ -395,6 +408,8 @@ def lc_map_vectors(x, n_vec: int, P_in: int, group, weight, P_out: int, y, ld_x:
     g, w = _map_arrays(group, weight)
     if len(g) != P_in:
         raise ValueError("group has %d entries, P_in = %d" % (len(g), P_in))
+    _need(x, _rows(n_vec, ld_x, P_in), "x")
+    _need(y, _rows(n_vec, ld_y, P_out), "y")
     _check(lib().lc_map_vectors(_dptr(x), int(n_vec), int(P_in), int(ld_x), g.ctypes.data, w.ctypes.data,
                                 int(P_out), _dptr(y), int(ld_y), _stream(stream)))
 
@@ -403,6 +418,8 @@ def lc_map_matrix(X, P_in: int, group, weight, P_out: int, Y, stream=None):
     g, w = _map_arrays(group, weight)
     if len(g) != P_in:
         raise ValueError("group has %d entries, P_in = %d" % (len(g), P_in))
+    _need(X, int(P_in) * int(P_in), "X")
+    _need(Y, int(P_out) * int(P_out), "Y")
     _check(lib().lc_map_matrix(_dptr(X), int(P_in), g.ctypes.data, w.ctypes.data, int(P_out), _dptr(Y),
                                _stream(stream)))
 
@@ -416,6 +433,8 @@ def lc_sample_covariance(x, n_mock: int, P: int, precision: int, C, stream=None)
 
 def lc_covcov(A, B, P: int, m_a: int, M: float, Cref=None, n_mock: int = 0, sd_lc=None, sd_smp=None,
               report: bool = True, stream=None) -> Optional[dict]:
+    for name, t in (("A", A), ("B", B), ("Cref", Cref), ("sd_lc", sd_lc), ("sd_smp", sd_smp)):
+        _need(t, int(P) * int(P), name)
     rep = lc_covcov_report() if report else None
     _check(lib().lc_covcov(_dptr(A), _dptr(B), int(P), int(m_a), float(M), _dptr(Cref), int(n_mock),
                            _dptr(sd_lc), _dptr(sd_smp), ctypes.byref(rep) if rep is not None else None,

@@ -279,3 +279,16 @@ def test_binding_refuses_short_buffers():
         lc.lc_covariance_general(xi, n_mock, P, 0, 1.0, 2.0, 50.0, lc.LC_FP64, None, None, C, report=False)
     with pytest.raises(ValueError, match="C"):
         lc.lc_sample_covariance(xi, n_mock, P, lc.LC_FP64, C[:-1])
+    counts = torch.zeros((3, n_r, n_mu), dtype=torch.int64)
+    with pytest.raises(ValueError, match="out"):
+        lc.lc_rebin_counts(counts, 3, n_r, n_mu, 2, 1, torch.zeros((3, 1, n_mu), dtype=torch.int64))
+    with pytest.raises(ValueError, match="counts"):
+        lc.lc_rebin_counts(counts, 4, n_r, n_mu, 1, 1, torch.zeros((4, n_r, n_mu), dtype=torch.int64))
+    g = np.zeros(P, dtype=np.int32)
+    w = np.ones(P)
+    with pytest.raises(ValueError, match="y"):   # rows of 2 at a stride of 3 need 3 n - 1 values
+        lc.lc_map_vectors(xi, n_mock, P, g, w, 2, torch.zeros((n_mock, 2), dtype=torch.float64), ld_y=3)
+    with pytest.raises(ValueError, match="Y"):
+        lc.lc_map_matrix(C, P, g, w, 2, torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError, match="sd_lc"):
+        lc.lc_covcov(C, C, P, 1, 50.0, None, n_mock, C[:1], None, report=False)
