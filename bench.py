@@ -318,21 +318,28 @@ def main():
         log("[bench] autotune: %s (%.1f s)" % (json.dumps(tuned), time.perf_counter() - t0))
 
     def step(events=None):
-        pl.build_cells(cell_units, args.sub)
+        # events: step start, mesh built, counted, xi, covariance and check
         if events:
             events[0].record(stream)
-        pl.count()
+        pl.build_cells(cell_units, args.sub)
         if events:
             events[1].record(stream)
+        pl.count()
+        if events:
+            events[2].record(stream)
         pl.xi_multipoles()
-        return pl.covariance(lc.LC_FP32_MFMA, report=True)
+        if events:
+            events[3].record(stream)
+        rep = pl.covariance(lc.LC_FP32_MFMA, report=True)
+        if events:
+            events[4].record(stream)
+        return rep
 
     for w in range(args.warmup):
         log("[bench] warmup step %d" % w)
         step()
     torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rep = None
@@ -341,7 +348,9 @@ def main():
         log("[bench] step %d done" % k)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    count_ms = [a.elapsed_time(b) for a, b in evs]
+    count_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    stage_ms = {name: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs]))
+                for i, name in enumerate(("cells", "count", "xi", "covariance_and_check"))}
     st = pl.stats_host()
     binned = st["binned"]
     cand = st["candidates"]
@@ -369,6 +378,7 @@ def main():
         "pair_tests_per_s": cand / kern_s,
         "binned_pairs_per_s": binned / kern_s,
         "pair_count_ms": float(np.mean(count_ms)),
+        "stage_ms": stage_ms,
         "inputs": {"generation_s": gen_s, "h2d_s": h2d_s, "h2d_bytes": int(cats.xyz.nbytes),
                    "note": "synthetic catalogues drawn on the host and copied once; not part of a step"},
         "candidates_per_step": cand,
